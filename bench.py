@@ -1,0 +1,179 @@
+"""Benchmark of the whole path on one GPU: project, enumerate, verify.
+
+One step = msm_project + msm_enumerate_pairs + msm_verify over the paper-scale
+mixture (n = 1,000,000, d = 128, ell = 128 bits, k = 8 blocks, h = 4,
+Euclidean eps = 0.5), inputs already resident in device memory. Prints one
+JSON line. ``value`` is points per second of whole steps.
+
+Usage: python bench.py [--steps K] [--warmup W] [--sigma-mode coord|radius]
+                       [--cpu-sample N | --no-cpu-baseline]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP32_MFMA_PEAK_TFLOPS = 157.3
+METRIC = "points/s + edges/s at n=1M,d=128,ℓ=128,h≤4; missing-edge ratio vs brute"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic(kernel, w, n, C, mH, mE, W):
+    """(amount, unit, bound) of algorithmic work per launch of a kernel.
+
+    Units per launch: a launch of the partition and bucket kernels covers n
+    points under each of the C combinations; k_verify covers the mH
+    candidate pairs; k_project_f32 the n x d x ell products.
+    """
+    sb = 8 * W  # bytes of one string
+    if kernel == "k_project_f32":
+        return 2.0 * n * w.d * w.ell / 1e12, "TFLOP/s", "mfma"
+    if kernel == "k_part_count":
+        return n * C * sb / 1e9, "GB/s", "hbm"
+    if kernel == "k_part_scatter":
+        return n * C * (sb + 8) / 1e9, "GB/s", "hbm"
+    if kernel == "k_bucket":
+        return (n * C * 8 + mH * 8) / 1e9, "GB/s", "hbm"
+    if kernel == "k_verify":
+        return (mH * (8 + 2 * 4 * w.d) + mE * 8) / 1e9, "GB/s", "hbm"
+    return None
+
+
+def cpu_baseline(w, X, R, sample):
+    """The oracle (FP64 project, MSM, verify) on the first `sample` rows."""
+    import numpy as np
+
+    from oracle import oracle as O
+    Xs = np.ascontiguousarray(X[:sample])
+    t0 = time.perf_counter()
+    S = O.project(Xs, R)
+    P = O.msm(S, w.ell, w.k, w.h)
+    O.verify(Xs, P, O.EUCLIDEAN, float(np.float32(w.eps)))
+    t = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+    return {"value": sample / t, "unit": "points/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {sample} of {w.n} points (FP64 project + MSM + verify), {t:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--sigma-mode", default="coord", choices=["coord", "radius"])
+    ap.add_argument("--cpu-sample", type=int, default=250_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: the MSM path here is built and measured on a single "
+              "MI355X (see the design notes for how it would shard).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_0904_3151_amd import inputs as I
+    from paper_0904_3151_amd import msm
+
+    w = I.PAPER_SCALE
+    log(f"generating {w.name} ({args.sigma_mode})")
+    X, R = I.workload_inputs(w, sigma_mode=args.sigma_mode)
+    n, W = w.n, (w.ell + 63) // 64
+    dev = torch.device("cuda:0")
+    Xd = torch.from_numpy(X).to(dev)
+    Rd = torch.from_numpy(R).to(dev)
+    S = torch.empty((n, W), dtype=torch.int64, device=dev)
+    ctx = msm.Context(0)
+    C = 1
+    for t in range(w.h):
+        C = C * (w.k - t) // (t + 1)
+
+    # size the output buffers with a count-only pass
+    msm.msm_project(ctx, Xd, Rd, S)
+    _, mH = msm.msm_enumerate_pairs(ctx, S, w.ell, w.k, w.h, cap=0)
+    pairs = torch.empty((max(1, int(mH * 1.05) + 1024), 2), dtype=torch.int32, device=dev)
+    verified = torch.empty_like(pairs)
+    log(f"hamming pairs {mH}")
+
+    def step():
+        msm.msm_project(ctx, Xd, Rd, S)
+        P, m = msm.msm_enumerate_pairs(ctx, S, w.ell, w.k, w.h, pairs=pairs)
+        V, kept = msm.msm_verify(ctx, Xd, P, w.metric, w.eps, out=verified)
+        return m, kept
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    msm.msm_profile_reset(ctx)
+    msm.msm_profile_enable(ctx, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        mH, mE = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    msm.msm_profile_enable(ctx, False)
+    prof = msm.msm_profile_read(ctx)
+
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    phase = {}
+    for name, (launches, total) in prof.items():
+        phase[name] = {"launches": launches, "avg_ms": total / max(launches, 1),
+                       "ms_per_step": total / args.steps}
+    t_enum = sum(v["ms_per_step"] for k, v in phase.items()
+                 if k in ("k_part_count", "k_part_scan", "k_part_scatter", "k_bucket", "k_big"))
+    dom = max(phase, key=lambda k: phase[k]["ms_per_step"])
+    roof = None
+    alg = algorithmic(dom, w, n, C, mH, mE, W)
+    if alg is not None:
+        amount, unit, bound = alg
+        achieved = amount / (phase[dom]["avg_ms"] / 1e3)
+        peak = FP32_MFMA_PEAK_TFLOPS if bound == "mfma" else HBM_PEAK_GBS
+        roof = {"kernel": dom, "bound": bound, "achieved": round(achieved, 2), "peak": peak, "unit": unit,
+                "frac": round(achieved / peak, 4), "traffic": None}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log(f"cpu baseline on {args.cpu_sample} points")
+        cpu = cpu_baseline(w, X, R, args.cpu_sample)
+
+    out = {
+        "metric": METRIC,
+        "value": round(n / (ms_step / 1e3), 1),
+        "unit": "points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": f"synthetic Gaussian mixture, sigma_mode={args.sigma_mode}",
+        "config": {"workload": w.name, "n": n, "d": w.d, "ell": w.ell, "k": w.k, "h": w.h, "eps": w.eps,
+                   "metric": w.metric, "combinations": C, "sigma_mode": args.sigma_mode},
+        "edges_per_s": {"hamming_pairs_per_s_enumerate": round(mH / (t_enum / 1e3), 1) if t_enum else None,
+                        "eps_pairs_per_s_total": round(mE / (ms_step / 1e3), 1)},
+        "counts": {"hamming_pairs": int(mH), "eps_pairs": int(mE)},
+        "kernels": {k: {kk: round(vv, 4) if isinstance(vv, float) else vv for kk, vv in v.items()}
+                    for k, v in sorted(phase.items())},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

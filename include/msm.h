@@ -1,0 +1,170 @@
+/*
+ * msm.h - C ABI of libmsm, neighbourhood-graph construction by the multiple
+ * sorting method (MSM) on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Uno, Sugiyama and Tsuda, "Efficient Construction of Neighborhood
+ * Graphs by the Multiple Sorting Method" (arXiv:0904.3151).
+ *
+ * The library computes the three steps of the method's data-parallel path:
+ *
+ *   msm_project          vectors -> ell-bit sign strings       (Section 3.2, eq. (3))
+ *   msm_enumerate_pairs  strings -> pairs within Hamming h     (Sections 2.1-2.2, eq. (1))
+ *   msm_verify           pairs   -> pairs within distance eps  (Section 4.1, Definition 1.1)
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Every data pointer is a DEVICE pointer on the context's device, owned by
+ *   the caller. The library never frees or keeps caller memory.
+ * - Host pointers are marked HOST. They are written before the call returns.
+ * - `stream` is a hipStream_t (NULL means the default stream). Work is
+ *   enqueued on it. Calls that return a count (`m_out`) synchronise the
+ *   stream before returning; msm_project does not synchronise.
+ * - Indices are 0-based uint32; n must be below 2^32.
+ * - X is FP32, n rows of d values, row i at X + i*ldx (ldx >= d, in floats).
+ * - R is FP32, d x ell, row-major: R[t*ell + c]; column c is the random
+ *   direction r_c of bit c.
+ * - S is uint64, n rows of W = ceil(ell/64) words. Bit c of row i is
+ *   (S[i*W + c/64] >> (c%64)) & 1. msm_project writes padding bits (at and
+ *   above ell) as 0; msm_enumerate_pairs ignores them.
+ * - A pair list is uint32 interleaved (i, j) with i < j: pair p is
+ *   pairs[2p], pairs[2p+1]. Its order is unspecified; it is a set.
+ * - Every call returns an msm_status; nothing throws across the ABI. On
+ *   failure msm_last_error(ctx) describes the cause.
+ * - A context may be used by one host thread at a time. Calls on one context
+ *   share its scratch memory, so they must be ordered on one stream.
+ */
+#ifndef MSM_H
+#define MSM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MSM_OK = 0,
+    MSM_E_INVALID = -1,     /* an argument is out of range or a needed pointer is NULL */
+    MSM_E_CAPACITY = -2,    /* the output did not fit; *m_out holds the required count */
+    MSM_E_UNSUPPORTED = -3, /* valid but outside what this build implements */
+    MSM_E_NOMEM = -4,       /* device scratch allocation failed */
+    MSM_E_HIP = -5          /* a HIP runtime call failed */
+} msm_status;
+
+typedef enum {
+    MSM_EUCLIDEAN = 0, /* Delta(x, y) = ||x - y||_2 */
+    MSM_COSINE = 1     /* Delta(x, y) = 1 - x.y / (||x|| ||y||), eq. (2); 1 if either is zero */
+} msm_metric;
+
+typedef struct msm_ctx msm_ctx;
+
+/* Library version as 10000*major + 100*minor + patch. */
+int32_t msm_version(void);
+
+/* Create a context on HIP device `device`. The context owns the scratch
+ * memory of the calls made through it; it grows on demand and is released
+ * by msm_destroy. Returns MSM_E_INVALID if out is NULL, MSM_E_HIP if the
+ * device cannot be selected. */
+msm_status msm_create(int32_t device, msm_ctx** out);
+
+/* Release a context and its scratch memory. NULL is ignored. The caller
+ * must make sure no work using the context is still running. */
+void msm_destroy(msm_ctx* ctx);
+
+/* Message for the last failed call on ctx ("" if none). The string is owned
+ * by the context and valid until its next call. ctx may be NULL, in which
+ * case the message of the last failed msm_create is returned. */
+const char* msm_last_error(const msm_ctx* ctx);
+
+/* Random-projection LSH, Section 3.2, eq. (3):
+ *   z_ic = sum_t X[i,t] * R[t,c],   bit c of S_i = 1 iff z_ic > 0, else 0.
+ * FP32 multiply-add with FP32 accumulation on the matrix cores.
+ *   X    DEVICE float[n rows, ldx stride]   input vectors
+ *   R    DEVICE float[d * ell]              projection matrix, row-major
+ *   S    DEVICE uint64[n * W]               output strings (fully written)
+ * Limits: n >= 0, 1 <= d, ldx >= d, 1 <= ell <= 256.
+ * Errors: MSM_E_INVALID for a NULL ctx, out-of-range sizes, or NULL X, R, S
+ * with n > 0. Asynchronous: returns once the work is enqueued. */
+msm_status msm_project(msm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
+                       const float* R, int32_t ell, uint64_t* S, void* stream);
+
+/* All pairs within Hamming distance h, Sections 2.1-2.2 and eq. (1):
+ *   { (i, j) : i < j, popcount(S_i xor S_j) <= h }
+ * found by blockwise masking: the ell bits are split into k blocks of
+ * nearly equal length (the first ell mod k blocks get one extra bit), and
+ * for each of the C(k, h) sets B of masked blocks the strings are grouped by
+ * their unmasked part; pairs inside a group are tested and each pair is
+ * written under exactly one B, so the output has no duplicates.
+ *   S      DEVICE uint64[n * W]       input strings
+ *   pairs  DEVICE uint32[2 * cap]     output pairs; may be NULL when cap == 0
+ *   m_out  HOST   int64               number of pairs (always written on OK
+ *                                     and on MSM_E_CAPACITY)
+ * The result set does not depend on k; k only changes the work.
+ * Limits: n < 2^32, 1 <= ell <= 256, 0 <= h < k <= min(ell, 64),
+ * C(k, h) <= 65536.
+ * Errors: MSM_E_INVALID (sizes, NULL pointers), MSM_E_UNSUPPORTED (k > 64
+ * or too many combinations), MSM_E_CAPACITY when the count exceeds cap:
+ * *m_out then holds the required count and the contents of pairs are
+ * undefined. pairs == NULL with cap == 0 is a count-only call. Synchronises
+ * `stream` before returning. */
+msm_status msm_enumerate_pairs(msm_ctx* ctx, const uint64_t* S, int64_t n, int32_t ell,
+                               int32_t k, int32_t h, uint32_t* pairs, int64_t cap,
+                               int64_t* m_out, void* stream);
+
+/* Verification step of Section 4.1: keep the pairs of a list whose true
+ * distance is at most eps (Definition 1.1). FP32 arithmetic: Euclidean
+ * compares sum (x_t - y_t)^2 with eps^2; cosine compares eq. (2) with eps.
+ *   X      DEVICE float[n rows, ldx stride]
+ *   pairs  DEVICE uint32[2 * m]         candidate pairs (i, j), both < n
+ *   out    DEVICE uint32[2 * cap]       kept pairs (may alias nothing else)
+ *   m_out  HOST   int64                 number kept
+ * Errors: MSM_E_INVALID (sizes, NULL pointers, unknown metric, eps < 0 or
+ * not finite, a pair index >= n: such pairs are skipped and reported),
+ * MSM_E_CAPACITY as for msm_enumerate_pairs. Pair buffers must be 8-byte
+ * aligned. Synchronises `stream`. */
+msm_status msm_verify(msm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
+                      const uint32_t* pairs, int64_t m, int32_t metric, float eps,
+                      uint32_t* out, int64_t cap, int64_t* m_out, void* stream);
+
+/* Exhaustive epsilon-neighbour enumeration, Definition 1.1: every (i, j),
+ * i < j, with Delta(x_i, x_j) <= eps. This is the judge for the
+ * missing-edge ratio of Section 4.2 (|F2| / |E*| on a subsample), not part
+ * of the MSM path. FP32 Gram-matrix screening on the matrix cores with a
+ * rounding band, then an FP64 evaluation of each screened pair from the
+ * FP32 inputs: the result is the FP64 definition. Euclidean compares the
+ * squared distance with eps^2; cosine uses eq. (2), 1 for a zero vector.
+ *   X      DEVICE float[n rows, ldx stride]
+ *   out    DEVICE uint32[2 * cap]     pairs (i, j), i < j, 8-byte aligned
+ *   m_out  HOST   int64               number of pairs
+ * Limits: n <= about 3e6 (the upper triangle of 64 x 64 tiles must stay
+ * below 2^31 workgroups). Errors as for msm_verify; MSM_E_CAPACITY when the
+ * count exceeds cap. Synchronises `stream`. */
+msm_status msm_bruteforce_eps(msm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
+                              int32_t metric, float eps, uint32_t* out, int64_t cap,
+                              int64_t* m_out, void* stream);
+
+/* Per-kernel timing. While enabled, every kernel launch of the context is
+ * bracketed by two HIP events on its stream (a few microseconds of overhead
+ * per launch). Timings accumulate per kernel name until msm_profile_reset. */
+typedef struct {
+    char name[48];     /* kernel name, NUL-terminated */
+    int64_t launches;  /* launches timed */
+    double total_ms;   /* summed event-to-event time */
+} msm_kernel_time;
+
+/* Turn timing on (enable != 0) or off. Errors: MSM_E_INVALID for NULL ctx. */
+msm_status msm_profile_enable(msm_ctx* ctx, int32_t enable);
+
+/* Wait for the recorded events and clear the totals. */
+msm_status msm_profile_reset(msm_ctx* ctx);
+
+/* Wait for the recorded events, then write up to cap HOST records to out.
+ * Returns the number of kernels with records (may exceed cap), or -1 on
+ * error (NULL ctx, cap < 0, out NULL with cap > 0, a HIP failure). */
+int32_t msm_profile_read(msm_ctx* ctx, msm_kernel_time* out, int32_t cap);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MSM_H */

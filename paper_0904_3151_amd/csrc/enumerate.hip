@@ -1,0 +1,782 @@
+// Multiple sorting method with blockwise masking (Sections 2.1-2.2) on gfx950.
+//
+// For every set B of h masked blocks the points must be grouped by their
+// B-masked string s^B, and pairs inside a group tested. Only grouping is
+// needed, not a full order (the paper's own radix-sort trick makes the same
+// observation), so the sort key is a 32-bit mix of the masked string rather
+// than the string itself:
+//
+//   1. partition  one MSD radix pass over HBM on the top r1 bits of the mix:
+//                 LDS histograms per tile (k_part_count), a column scan of
+//                 the (tile, bucket) counts (k_part_scan), and a scatter of
+//                 (mix << 32 | index) into bucket order (k_part_scatter).
+//   2. bucket     one workgroup per bucket (about 512 points): a stable LSD
+//                 radix sort in LDS on the next 16 bits of the mix (two 8-bit
+//                 digits, ranked with wave64 ballots and a wave prefix scan),
+//                 segmentation into runs of equal mix, and a flat, balanced
+//                 loop over all pairs inside runs (k_bucket).
+//   3. overflow   buckets larger than the LDS capacity are tested tile by
+//                 tile straight from HBM (k_big).
+//
+// Equal masked strings always share a mix, so no pair is lost. Different
+// strings can share a mix; that only adds candidates, because the pair test
+// below is exact:
+//
+//   x = s_i xor s_j;  keep iff popcount(x) <= h            (Hamming filter)
+//                     and x has no bit outside the blocks of B  (s_i^B == s_j^B)
+//                     and B is the canonical set for the blocks where x != 0.
+//
+// Canonical set: a pair whose differing blocks form D (|D| <= h) falls into
+// one group under every h-set B containing D. It is written only under
+// D plus the smallest blocks not in D, i.e. iff D is a subset of B and every
+// block of B above the smallest unmasked block is in D. So each pair comes
+// out exactly once without any exchange between combinations.
+#include "msm_internal.h"
+
+#include <algorithm>
+#include <vector>
+
+namespace {
+
+constexpr int MAXW = 4;
+constexpr int MAXK = 64;
+constexpr int PART_THREADS = 256;
+constexpr int SCAN_THREADS = 1024;
+constexpr int BK_THREADS = 256;
+constexpr int BK_WAVES = BK_THREADS / 64;
+constexpr int BK_MAXB = 4;                        // 64-element batches per wave
+constexpr int BK_CAP = BK_WAVES * 64 * BK_MAXB;   // largest bucket sorted in LDS
+constexpr int BK_PAIR_CHUNK = 8;                  // consecutive pairs per lane
+constexpr int BIG_TILE = 256;
+constexpr int MAX_BUCKETS = 8192;
+constexpr int TARGET_BUCKET = 512;
+
+struct Combo {             // one set B of masked blocks
+    uint64_t keep[MAXW];   // characters below ell outside the blocks of B
+    uint64_t hi;           // blocks of B above the smallest block not in B
+    uint64_t pad[3];
+};
+static_assert(sizeof(Combo) == 64, "Combo layout");
+
+struct Ovf {
+    uint32_t c, beg, m, pad;
+};
+
+struct Params {
+    const uint64_t* S;
+    int64_t n;
+    const Combo* combos;     // combinations of this launch group
+    const uint64_t* bm;      // [k][MAXW] block masks
+    int k, h;
+    uint64_t valid[MAXW];    // bits below ell
+    int r1;                  // bucket bits (top bits of the mix)
+    int nb;                  // 1 << r1
+    int sort_lo;             // runs share mix >> sort_lo
+    int T, nt;               // partition tile size and count
+    uint32_t* counts;        // [c][t][b] tile counts, then tile offsets
+    uint32_t* base;          // [c][nb + 1] bucket starts
+    uint64_t* part;          // [c][n] (mix << 32 | index) in bucket order
+    uint32_t* pairs;
+    unsigned long long cap;
+    unsigned long long* counter;
+    Ovf* ovf;
+    uint32_t* ovf_count;
+};
+
+__device__ __forceinline__ uint64_t mix64(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+template <int W>
+__device__ __forceinline__ uint32_t masked_mix(const uint64_t (&s)[W], const uint64_t (&keep)[W])
+{
+    uint64_t z = 0x9e3779b97f4a7c15ull;
+#pragma unroll
+    for (int w = 0; w < W; ++w) z = mix64(z ^ (s[w] & keep[w]));
+    return (uint32_t)(z >> 32);
+}
+
+template <int W>
+__device__ __forceinline__ void load_string(const uint64_t* __restrict__ S, uint64_t i, uint64_t (&s)[W])
+{
+    const uint64_t* p = S + i * W;
+#pragma unroll
+    for (int w = 0; w < W; ++w) s[w] = p[w];
+}
+
+template <int W>
+__device__ __forceinline__ void load_keep(const Combo* cb, uint64_t (&keep)[W])
+{
+#pragma unroll
+    for (int w = 0; w < W; ++w) keep[w] = cb->keep[w];
+}
+
+// -------------------------------------------------------------------------
+// 1. partition
+
+template <int W>
+__global__ __launch_bounds__(PART_THREADS) void k_part_count(Params p)
+{
+    extern __shared__ uint32_t hist[];
+    const int cl = blockIdx.x;
+    const int t = blockIdx.y;
+    uint64_t keep[W];
+    load_keep<W>(p.combos + cl, keep);
+    for (int b = threadIdx.x; b < p.nb; b += PART_THREADS) hist[b] = 0;
+    __syncthreads();
+    const int64_t beg = (int64_t)t * p.T;
+    const int64_t end = min(p.n, beg + p.T);
+    for (int64_t i = beg + threadIdx.x; i < end; i += PART_THREADS) {
+        uint64_t s[W];
+        load_string<W>(p.S, (uint64_t)i, s);
+        const uint32_t mx = masked_mix<W>(s, keep);
+        const uint32_t b = p.r1 ? (mx >> (32 - p.r1)) : 0u;
+        atomicAdd(&hist[b], 1u);
+    }
+    __syncthreads();
+    uint32_t* out = p.counts + ((size_t)cl * p.nt + t) * p.nb;
+    for (int b = threadIdx.x; b < p.nb; b += PART_THREADS) out[b] = hist[b];
+}
+
+// Per combination: counts[t][b] -> offset of tile t inside bucket b, and
+// base[b] = start of bucket b.
+__global__ __launch_bounds__(SCAN_THREADS) void k_part_scan(Params p)
+{
+    extern __shared__ uint32_t tot[];  // nb totals, then one word per wave
+    const int cl = blockIdx.x;
+    uint32_t* cnt = p.counts + (size_t)cl * p.nt * p.nb;
+    for (int b = threadIdx.x; b < p.nb; b += SCAN_THREADS) {
+        uint32_t run = 0;
+        int t = 0;
+        for (; t + 8 <= p.nt; t += 8) {
+            uint32_t v[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) v[q] = cnt[(size_t)(t + q) * p.nb + b];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                cnt[(size_t)(t + q) * p.nb + b] = run;
+                run += v[q];
+            }
+        }
+        for (; t < p.nt; ++t) {
+            const uint32_t v = cnt[(size_t)t * p.nb + b];
+            cnt[(size_t)t * p.nb + b] = run;
+            run += v;
+        }
+        tot[b] = run;
+    }
+    __syncthreads();
+    uint32_t* wsum = tot + p.nb;
+    const int per = (p.nb + SCAN_THREADS - 1) / SCAN_THREADS;
+    const int b0 = threadIdx.x * per;
+    const int b1 = min(p.nb, b0 + per);
+    uint32_t s = 0;
+    for (int b = b0; b < b1; ++b) s += tot[b];
+    const uint32_t incl = msm::wave_incl_scan(s);
+    const int wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 63) wsum[wave] = incl;
+    __syncthreads();
+    uint32_t pre = 0;
+    for (int w = 0; w < wave; ++w) pre += wsum[w];
+    uint32_t run = pre + incl - s;
+    uint32_t* base = p.base + (size_t)cl * (p.nb + 1);
+    for (int b = b0; b < b1; ++b) {
+        const uint32_t v = tot[b];
+        base[b] = run;
+        run += v;
+    }
+    if (threadIdx.x == 0) base[p.nb] = (uint32_t)p.n;
+}
+
+template <int W>
+__global__ __launch_bounds__(PART_THREADS) void k_part_scatter(Params p)
+{
+    extern __shared__ uint32_t cursor[];
+    const int cl = blockIdx.x;
+    const int t = blockIdx.y;
+    uint64_t keep[W];
+    load_keep<W>(p.combos + cl, keep);
+    const uint32_t* off = p.counts + ((size_t)cl * p.nt + t) * p.nb;
+    const uint32_t* base = p.base + (size_t)cl * (p.nb + 1);
+    for (int b = threadIdx.x; b < p.nb; b += PART_THREADS) cursor[b] = base[b] + off[b];
+    __syncthreads();
+    uint64_t* part = p.part + (size_t)cl * p.n;
+    const int64_t beg = (int64_t)t * p.T;
+    const int64_t end = min(p.n, beg + p.T);
+    for (int64_t i = beg + threadIdx.x; i < end; i += PART_THREADS) {
+        uint64_t s[W];
+        load_string<W>(p.S, (uint64_t)i, s);
+        const uint32_t mx = masked_mix<W>(s, keep);
+        const uint32_t b = p.r1 ? (mx >> (32 - p.r1)) : 0u;
+        const uint32_t pos = atomicAdd(&cursor[b], 1u);
+        part[pos] = ((uint64_t)mx << 32) | (uint64_t)(uint32_t)i;
+    }
+}
+
+// -------------------------------------------------------------------------
+// Exact pair test of one candidate (see the file comment).
+
+template <int W>
+__device__ __forceinline__ bool pair_ok(const uint64_t* a, const uint64_t* b, const Params& p,
+                                        const uint64_t (&keep)[W], uint64_t hi,
+                                        const uint64_t* __restrict__ bmL)
+{
+    uint64_t x[W];
+    int ham = 0;
+    uint64_t outside = 0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+        x[w] = (a[w] ^ b[w]) & p.valid[w];
+        ham += __popcll(x[w]);
+        outside |= x[w] & keep[w];
+    }
+    bool ok = (ham <= p.h) && (outside == 0);
+    uint64_t need = hi;
+    while (ok && need) {
+        const int blk = __builtin_ctzll(need);
+        need &= need - 1;
+        uint64_t any = 0;
+#pragma unroll
+        for (int w = 0; w < W; ++w) any |= x[w] & bmL[blk * W + w];
+        ok = any != 0;
+    }
+    return ok;
+}
+
+__device__ __forceinline__ void write_pair(const Params& p, bool ok, unsigned long long slot,
+                                           uint32_t i, uint32_t j)
+{
+    if (ok && slot < p.cap) {
+        const uint32_t lo = i < j ? i : j;
+        const uint32_t hi = i < j ? j : i;
+        *reinterpret_cast<uint2*>(p.pairs + 2 * slot) = make_uint2(lo, hi);
+    }
+}
+
+// Exclusive prefix over values laid out as position = wave*256 + b*64 + lane
+// (the element layout of k_bucket). Returns the block total.
+__device__ __forceinline__ uint32_t scan_wbl(const uint32_t (&v)[BK_MAXB], uint32_t (&ex)[BK_MAXB],
+                                             uint32_t* tmp)
+{
+    const int wave = threadIdx.x >> 6;
+    uint32_t carry = 0;
+#pragma unroll
+    for (int b = 0; b < BK_MAXB; ++b) {
+        const uint32_t incl = msm::wave_incl_scan(v[b]);
+        ex[b] = carry + incl - v[b];
+        carry += __shfl(incl, 63, 64);
+    }
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) tmp[wave] = carry;
+    __syncthreads();
+    uint32_t pre = 0, total = 0;
+#pragma unroll
+    for (int w = 0; w < BK_WAVES; ++w) {
+        const uint32_t t = tmp[w];
+        if (w < wave) pre += t;
+        total += t;
+    }
+#pragma unroll
+    for (int b = 0; b < BK_MAXB; ++b) ex[b] += pre;
+    return total;
+}
+
+// -------------------------------------------------------------------------
+// 2. one bucket per workgroup
+
+template <int W>
+__global__ __launch_bounds__(BK_THREADS) void k_bucket(Params p)
+{
+    __shared__ uint64_t keysB[BK_CAP];
+    __shared__ uint64_t sl[BK_CAP * W];
+    __shared__ uint32_t whist[BK_WAVES][256];
+    __shared__ uint16_t headPos[BK_CAP + 1];
+    __shared__ uint16_t runS[BK_CAP];
+    __shared__ uint16_t runL[BK_CAP];
+    __shared__ uint32_t runP[BK_CAP + 1];
+    __shared__ uint64_t bmL[MAXK * W];
+    __shared__ uint32_t tmp[BK_WAVES];
+
+    const int bk = blockIdx.x;
+    const int cl = blockIdx.y;
+    const uint32_t* base = p.base + (size_t)cl * (p.nb + 1);
+    const uint32_t beg = base[bk];
+    const uint32_t cnt = base[bk + 1] - beg;
+    if (cnt < 2) return;
+    if (cnt > (uint32_t)BK_CAP) {
+        if (threadIdx.x == 0) {
+            const uint32_t o = atomicAdd(p.ovf_count, 1u);
+            p.ovf[o] = Ovf{(uint32_t)cl, beg, cnt, 0u};
+        }
+        return;
+    }
+    const int m = (int)cnt;
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const Combo* cb = p.combos + cl;
+    uint64_t keep[W];
+    load_keep<W>(cb, keep);
+    const uint64_t hi = cb->hi;
+    for (int e = threadIdx.x; e < p.k * W; e += BK_THREADS) bmL[e] = p.bm[(e / W) * MAXW + (e % W)];
+
+    const uint64_t* part = p.part + (size_t)cl * p.n + beg;
+    uint64_t key[BK_MAXB];
+    int pos[BK_MAXB];
+    bool valid[BK_MAXB];
+#pragma unroll
+    for (int b = 0; b < BK_MAXB; ++b) {
+        pos[b] = wave * (64 * BK_MAXB) + b * 64 + lane;
+        valid[b] = pos[b] < m;
+        key[b] = valid[b] ? part[pos[b]] : ~0ull;
+    }
+
+    // Stable LSD radix sort on mix bits [sort_lo, sort_lo + 16): two 8-bit
+    // digits. Lanes with equal digits in a batch of 64 find each other with
+    // eight ballots; ranks follow position order, so each pass is stable.
+#pragma unroll
+    for (int pass = 0; pass < 2; ++pass) {
+        const int sh = 32 + p.sort_lo + 8 * pass;
+        for (int i = lane; i < 256; i += 64) whist[wave][i] = 0;
+        __syncthreads();
+        uint32_t loc[BK_MAXB];
+        uint32_t dg[BK_MAXB];
+#pragma unroll
+        for (int b = 0; b < BK_MAXB; ++b) {
+            dg[b] = (uint32_t)(key[b] >> sh) & 0xFFu;
+            uint64_t peers = __ballot(valid[b]);
+#pragma unroll
+            for (int bit = 0; bit < 8; ++bit) {
+                const bool set = (dg[b] >> bit) & 1u;
+                const uint64_t bb = __ballot(set);
+                peers &= set ? bb : ~bb;
+            }
+            const uint32_t rank = (uint32_t)__popcll(peers & msm::lanemask_lt());
+            uint32_t old = 0;
+            if (valid[b]) old = whist[wave][dg[b]];
+            if (valid[b] && rank == 0) whist[wave][dg[b]] = old + (uint32_t)__popcll(peers);
+            loc[b] = old + rank;
+        }
+        __syncthreads();
+        {
+            const int dgt = threadIdx.x;  // BK_THREADS == 256 digits
+            uint32_t s = 0;
+#pragma unroll
+            for (int w = 0; w < BK_WAVES; ++w) {
+                const uint32_t v = whist[w][dgt];
+                whist[w][dgt] = s;
+                s += v;
+            }
+            const uint32_t incl = msm::wave_incl_scan(s);
+            __syncthreads();
+            if (lane == 63) tmp[wave] = incl;
+            __syncthreads();
+            uint32_t pre = 0;
+            for (int w = 0; w < wave; ++w) pre += tmp[w];
+            const uint32_t ex = pre + incl - s;
+#pragma unroll
+            for (int w = 0; w < BK_WAVES; ++w) whist[w][dgt] += ex;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int b = 0; b < BK_MAXB; ++b)
+            if (valid[b]) keysB[whist[wave][dg[b]] + loc[b]] = key[b];
+        __syncthreads();
+#pragma unroll
+        for (int b = 0; b < BK_MAXB; ++b) key[b] = valid[b] ? keysB[pos[b]] : ~0ull;
+    }
+
+    // Runs of equal mix >> sort_lo.
+    const int rsh = 32 + p.sort_lo;
+    uint32_t head[BK_MAXB], nextHead[BK_MAXB];
+#pragma unroll
+    for (int b = 0; b < BK_MAXB; ++b) {
+        const uint32_t rk = (uint32_t)(key[b] >> rsh);
+        head[b] = valid[b] && (pos[b] == 0 || (uint32_t)(keysB[pos[b] - 1] >> rsh) != rk);
+        nextHead[b] = valid[b] && (pos[b] + 1 == m || (uint32_t)(keysB[pos[b] + 1] >> rsh) != rk);
+    }
+    uint32_t ex[BK_MAXB];
+    const uint32_t nruns = scan_wbl(head, ex, tmp);
+#pragma unroll
+    for (int b = 0; b < BK_MAXB; ++b)
+        if (head[b]) headPos[ex[b]] = (uint16_t)pos[b];
+    if (threadIdx.x == 0) headPos[nruns] = (uint16_t)m;
+    __syncthreads();
+
+    // Runs of length >= 2 with their pair counts.
+    uint32_t isLong[BK_MAXB], npair[BK_MAXB], len[BK_MAXB];
+#pragma unroll
+    for (int b = 0; b < BK_MAXB; ++b) {
+        const int r = pos[b];
+        len[b] = r < (int)nruns ? (uint32_t)(headPos[r + 1] - headPos[r]) : 0u;
+        isLong[b] = len[b] >= 2;
+        npair[b] = isLong[b] ? len[b] * (len[b] - 1) / 2 : 0u;
+    }
+    uint32_t exL[BK_MAXB], exP[BK_MAXB];
+    const uint32_t nlong = scan_wbl(isLong, exL, tmp);
+    const uint32_t P = scan_wbl(npair, exP, tmp);
+#pragma unroll
+    for (int b = 0; b < BK_MAXB; ++b)
+        if (isLong[b]) {
+            runS[exL[b]] = headPos[pos[b]];
+            runL[exL[b]] = (uint16_t)len[b];
+            runP[exL[b]] = exP[b];
+        }
+    if (threadIdx.x == 0) runP[nlong] = P;
+    // Stage the strings of run members in sorted order.
+#pragma unroll
+    for (int b = 0; b < BK_MAXB; ++b)
+        if (valid[b] && !(head[b] && nextHead[b])) {
+            const uint64_t idx = (uint32_t)key[b];
+#pragma unroll
+            for (int w = 0; w < W; ++w) sl[pos[b] * W + w] = p.S[idx * W + w];
+        }
+    __syncthreads();
+    if (P == 0) return;
+
+    // Flat loop over all pairs (a < b) inside runs, row-major per run; each
+    // lane takes BK_PAIR_CHUNK consecutive pairs.
+    for (uint32_t t0 = 0; t0 < P; t0 += BK_THREADS * BK_PAIR_CHUNK) {
+        const uint32_t t = t0 + threadIdx.x * BK_PAIR_CHUNK;
+        int r = 0, a = 0, bb = 1, L = 2, s0 = 0;
+        if (t < P) {
+            int lo = 0, hi2 = (int)nlong;
+            while (hi2 - lo > 1) {
+                const int mid = (lo + hi2) >> 1;
+                if (runP[mid] <= t) lo = mid;
+                else hi2 = mid;
+            }
+            r = lo;
+            L = runL[r];
+            s0 = runS[r];
+            const uint32_t u = t - runP[r];
+            // row a of the upper triangle starts at a (2L - a - 1) / 2
+            const float q = (float)(2 * L - 1);
+            int aa = (int)((q - sqrtf(q * q - 8.0f * (float)u)) * 0.5f);
+            aa = max(0, min(aa, L - 2));
+            while (aa < L - 2 && (uint32_t)((aa + 1) * (2 * L - aa - 2) / 2) <= u) ++aa;
+            while (aa > 0 && (uint32_t)(aa * (2 * L - aa - 1) / 2) > u) --aa;
+            a = aa;
+            bb = a + 1 + (int)(u - (uint32_t)(a * (2 * L - a - 1) / 2));
+        }
+        for (int q = 0; q < BK_PAIR_CHUNK; ++q) {
+            const bool live = t + q < P;
+            bool ok = false;
+            uint32_t i = 0, j = 0;
+            if (live) {
+                const int pa = s0 + a, pb = s0 + bb;
+                ok = pair_ok<W>(&sl[pa * W], &sl[pb * W], p, keep, hi, bmL);
+                i = (uint32_t)keysB[pa];
+                j = (uint32_t)keysB[pb];
+                if (++bb == L) {
+                    ++a;
+                    bb = a + 1;
+                    if (a >= L - 1) {
+                        ++r;
+                        a = 0;
+                        bb = 1;
+                        if (r < (int)nlong) {
+                            L = runL[r];
+                            s0 = runS[r];
+                        }
+                    }
+                }
+            }
+            const unsigned long long slot = msm::wave_append(ok, p.counter);
+            write_pair(p, ok, slot, i, j);
+        }
+    }
+}
+
+// -------------------------------------------------------------------------
+// 3. buckets above BK_CAP: all pairs, tile against tile, from HBM. A pair
+// is tested only when the full 32-bit mixes agree.
+
+template <int W>
+__global__ __launch_bounds__(BIG_TILE) void k_big(Params p, const Ovf* __restrict__ ovf,
+                                                 const uint64_t* __restrict__ tile0, int novf)
+{
+    __shared__ uint64_t kR[BIG_TILE], kC[BIG_TILE];
+    __shared__ uint64_t sR[BIG_TILE * W], sC[BIG_TILE * W];
+    __shared__ uint64_t bmL[MAXK * W];
+    const uint64_t tix = blockIdx.x;
+    int lo = 0, hi2 = novf;
+    while (hi2 - lo > 1) {
+        const int mid = (lo + hi2) >> 1;
+        if (tile0[mid] <= tix) lo = mid;
+        else hi2 = mid;
+    }
+    const Ovf e = ovf[lo];
+    const int64_t nT = (e.m + BIG_TILE - 1) / BIG_TILE;
+    const int64_t u = (int64_t)(tix - tile0[lo]);
+    // (ta, tb), ta <= tb, row-major over the upper triangle with diagonal
+    const double q = (double)(2 * nT + 1);
+    int64_t ta = (int64_t)((q - sqrt(q * q - 8.0 * (double)u)) * 0.5);
+    ta = max<int64_t>(0, min<int64_t>(ta, nT - 1));
+    while (ta < nT - 1 && (ta + 1) * (2 * nT - ta) / 2 <= u) ++ta;
+    while (ta > 0 && ta * (2 * nT - ta + 1) / 2 > u) --ta;
+    const int64_t tb = ta + (u - ta * (2 * nT - ta + 1) / 2);
+
+    const Combo* cb = p.combos + e.c;
+    uint64_t keep[W];
+    load_keep<W>(cb, keep);
+    const uint64_t hi = cb->hi;
+    for (int x = threadIdx.x; x < p.k * W; x += BIG_TILE) bmL[x] = p.bm[(x / W) * MAXW + (x % W)];
+    const uint64_t* part = p.part + (size_t)e.c * p.n + e.beg;
+    const int64_t ra = ta * BIG_TILE + threadIdx.x;
+    const int64_t ca = tb * BIG_TILE + threadIdx.x;
+    const bool rv = ra < (int64_t)e.m;
+    const bool cv = ca < (int64_t)e.m;
+    kR[threadIdx.x] = rv ? part[ra] : 0ull;
+    kC[threadIdx.x] = cv ? part[ca] : 0ull;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+        sR[threadIdx.x * W + w] = rv ? p.S[(uint64_t)(uint32_t)kR[threadIdx.x] * W + w] : 0ull;
+        sC[threadIdx.x * W + w] = cv ? p.S[(uint64_t)(uint32_t)kC[threadIdx.x] * W + w] : 0ull;
+    }
+    __syncthreads();
+    const int ncol = (int)min<int64_t>(BIG_TILE, (int64_t)e.m - tb * BIG_TILE);
+    const uint32_t mine = (uint32_t)(kR[threadIdx.x] >> 32);
+    const bool diag = ta == tb;
+    for (int jj = 0; jj < ncol; ++jj) {
+        const uint64_t kc = kC[jj];
+        bool ok = rv && (!diag || jj > (int)threadIdx.x) && (uint32_t)(kc >> 32) == mine;
+        if (ok) ok = pair_ok<W>(&sR[threadIdx.x * W], &sC[jj * W], p, keep, hi, bmL);
+        const unsigned long long slot = msm::wave_append(ok, p.counter);
+        write_pair(p, ok, slot, (uint32_t)kR[threadIdx.x], (uint32_t)kc);
+    }
+}
+
+__global__ void k_zero_u64(unsigned long long* a, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = 0ull;
+}
+
+__global__ void k_zero_u32(uint32_t* a, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = 0u;
+}
+
+int64_t binom(int a, int b)
+{
+    if (b < 0 || b > a) return 0;
+    int64_t r = 1;
+    for (int t = 1; t <= b; ++t) {
+        r = r * (a - b + t) / t;
+        if (r > (1ll << 40)) return r;
+    }
+    return r;
+}
+
+template <int W>
+msm_status run_enumerate(msm_ctx* ctx, const uint64_t* S, int64_t n, int ell, int k, int h,
+                         uint32_t* pairs, int64_t cap, int64_t* m_out, hipStream_t stream)
+{
+    // Blocks of nearly equal length: the first ell mod k get one extra bit.
+    std::vector<uint64_t> bm((size_t)k * MAXW, 0ull);
+    {
+        int pos = 0;
+        for (int b = 0; b < k; ++b) {
+            const int len = ell / k + (b < ell % k ? 1 : 0);
+            for (int c = pos; c < pos + len; ++c) bm[(size_t)b * MAXW + (c >> 6)] |= 1ull << (c & 63);
+            pos += len;
+        }
+    }
+    uint64_t valid[MAXW] = {0, 0, 0, 0};
+    for (int c = 0; c < ell; ++c) valid[c >> 6] |= 1ull << (c & 63);
+
+    // All h-subsets of the k blocks.
+    std::vector<Combo> combos;
+    {
+        std::vector<int> sel(h);
+        for (int t = 0; t < h; ++t) sel[t] = t;
+        while (true) {
+            Combo cb{};
+            uint64_t Bm = 0;
+            for (int t = 0; t < h; ++t) Bm |= 1ull << sel[t];
+            for (int w = 0; w < MAXW; ++w) {
+                uint64_t kw = valid[w];
+                for (int t = 0; t < h; ++t) kw &= ~bm[(size_t)sel[t] * MAXW + w];
+                cb.keep[w] = kw;
+            }
+            int lowest_kept = 0;
+            while (lowest_kept < k && ((Bm >> lowest_kept) & 1ull)) ++lowest_kept;
+            uint64_t hi = 0;
+            for (int b = lowest_kept + 1; b < k; ++b)
+                if ((Bm >> b) & 1ull) hi |= 1ull << b;
+            cb.hi = hi;
+            combos.push_back(cb);
+            int t = h - 1;
+            while (t >= 0 && sel[t] == k - h + t) --t;
+            if (t < 0) break;
+            sel[t]++;
+            for (int u = t + 1; u < h; ++u) sel[u] = sel[u - 1] + 1;
+        }
+    }
+    const int C = (int)combos.size();
+
+    // Partition shape.
+    int r1 = 0;
+    while (r1 < 13 && ((int64_t)1 << r1) * TARGET_BUCKET < n) ++r1;
+    const int nb = 1 << r1;
+    const int sort_lo = 32 - r1 - 16;
+    int T = 4096;
+    while ((n + T - 1) / T > 65535) T *= 2;
+    const int nt = (int)((n + T - 1) / T);
+
+    // Combinations per launch group, bounded by scratch size.
+    const size_t per_combo = msm::align_up((size_t)n * 8, 256) + msm::align_up((size_t)nt * nb * 4, 256) +
+                             msm::align_up((size_t)(nb + 1) * 4, 256) + msm::align_up((size_t)nb * sizeof(Ovf), 256);
+    const size_t budget = (size_t)3 << 30;
+    int Cg = (int)std::max<size_t>(1, std::min<size_t>((size_t)C, budget / per_combo));
+    Cg = std::min(Cg, 65535);
+
+    msm::Carver cv;
+    cv.take<Combo>((size_t)C);
+    cv.take<uint64_t>((size_t)k * MAXW);
+    cv.take<unsigned long long>(4);
+    cv.take<uint32_t>(4);
+    cv.take<uint64_t>((size_t)Cg * n);
+    cv.take<uint32_t>((size_t)Cg * nt * nb);
+    cv.take<uint32_t>((size_t)Cg * (nb + 1));
+    cv.take<Ovf>((size_t)Cg * nb);
+    cv.take<uint64_t>((size_t)Cg * nb + 1);
+    void* scr = nullptr;
+    msm_status st = msm::scratch(ctx, cv.off, stream, &scr);
+    if (st != MSM_OK) return st;
+    msm::Carver c2;
+    c2.base = static_cast<char*>(scr);
+    Combo* d_combos = c2.take<Combo>((size_t)C);
+    uint64_t* d_bm = c2.take<uint64_t>((size_t)k * MAXW);
+    unsigned long long* d_counter = c2.take<unsigned long long>(4);
+    uint32_t* d_ovfc = c2.take<uint32_t>(4);
+    uint64_t* d_part = c2.take<uint64_t>((size_t)Cg * n);
+    uint32_t* d_counts = c2.take<uint32_t>((size_t)Cg * nt * nb);
+    uint32_t* d_base = c2.take<uint32_t>((size_t)Cg * (nb + 1));
+    Ovf* d_ovf = c2.take<Ovf>((size_t)Cg * nb);
+    uint64_t* d_tile0 = c2.take<uint64_t>((size_t)Cg * nb + 1);
+
+    MSM_HIP(ctx, hipMemcpyAsync(d_combos, combos.data(), sizeof(Combo) * C, hipMemcpyHostToDevice, stream));
+    MSM_HIP(ctx, hipMemcpyAsync(d_bm, bm.data(), sizeof(uint64_t) * bm.size(), hipMemcpyHostToDevice, stream));
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, stream, d_counter, 4);
+
+    Params p{};
+    p.S = S;
+    p.n = n;
+    p.bm = d_bm;
+    p.k = k;
+    p.h = h;
+    for (int w = 0; w < MAXW; ++w) p.valid[w] = valid[w];
+    p.r1 = r1;
+    p.nb = nb;
+    p.sort_lo = sort_lo;
+    p.T = T;
+    p.nt = nt;
+    p.counts = d_counts;
+    p.base = d_base;
+    p.part = d_part;
+    p.pairs = pairs;
+    p.cap = (unsigned long long)cap;
+    p.counter = d_counter;
+    p.ovf = d_ovf;
+    p.ovf_count = d_ovfc;
+
+    std::vector<Ovf> hovf;
+    std::vector<uint64_t> htile;
+    for (int c0 = 0; c0 < C; c0 += Cg) {
+        const int cc = std::min(Cg, C - c0);
+        p.combos = d_combos + c0;
+        hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, stream, d_ovfc, 4);
+        {
+            msm::KernelTimer kt(ctx, stream, "k_part_count");
+            hipLaunchKernelGGL((k_part_count<W>), dim3(cc, nt), dim3(PART_THREADS), nb * sizeof(uint32_t), stream, p);
+        }
+        {
+            msm::KernelTimer kt(ctx, stream, "k_part_scan");
+            hipLaunchKernelGGL(k_part_scan, dim3(cc), dim3(SCAN_THREADS), (nb + 32) * sizeof(uint32_t), stream, p);
+        }
+        {
+            msm::KernelTimer kt(ctx, stream, "k_part_scatter");
+            hipLaunchKernelGGL((k_part_scatter<W>), dim3(cc, nt), dim3(PART_THREADS), nb * sizeof(uint32_t), stream,
+                               p);
+        }
+        {
+            msm::KernelTimer kt(ctx, stream, "k_bucket");
+            hipLaunchKernelGGL((k_bucket<W>), dim3(nb, cc), dim3(BK_THREADS), 0, stream, p);
+        }
+        MSM_HIP(ctx, hipGetLastError());
+        MSM_HIP(ctx, hipMemcpyAsync(ctx->host_words, d_ovfc, sizeof(uint32_t), hipMemcpyDeviceToHost, stream));
+        MSM_HIP(ctx, hipStreamSynchronize(stream));
+        const uint32_t novf = *reinterpret_cast<uint32_t*>(ctx->host_words);
+        if (novf > 0) {
+            hovf.resize(novf);
+            MSM_HIP(ctx, hipMemcpy(hovf.data(), d_ovf, sizeof(Ovf) * novf, hipMemcpyDeviceToHost));
+            htile.assign(novf + 1, 0);
+            for (uint32_t o = 0; o < novf; ++o) {
+                const uint64_t t = (hovf[o].m + BIG_TILE - 1) / BIG_TILE;
+                htile[o + 1] = htile[o] + t * (t + 1) / 2;
+            }
+            const uint64_t tiles = htile[novf];
+            if (tiles > 0x7FFFFFFFull)
+                return msm::fail(ctx, MSM_E_UNSUPPORTED,
+                                 "msm_enumerate_pairs: a group of %u equal strings is too large",
+                                 (unsigned)hovf[0].m);
+            MSM_HIP(ctx, hipMemcpyAsync(d_tile0, htile.data(), sizeof(uint64_t) * (novf + 1),
+                                        hipMemcpyHostToDevice, stream));
+            msm::KernelTimer kt(ctx, stream, "k_big");
+            hipLaunchKernelGGL((k_big<W>), dim3((unsigned)tiles), dim3(BIG_TILE), 0, stream, p, d_ovf,
+                               d_tile0, (int)novf);
+            MSM_HIP(ctx, hipGetLastError());
+        }
+    }
+    MSM_HIP(ctx, hipMemcpyAsync(ctx->host_words, d_counter, sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                                stream));
+    MSM_HIP(ctx, hipStreamSynchronize(stream));
+    const int64_t m = (int64_t)ctx->host_words[0];
+    *m_out = m;
+    if (m > cap && !(pairs == nullptr && cap == 0))
+        return msm::fail(ctx, MSM_E_CAPACITY, "msm_enumerate_pairs: %lld pairs do not fit in cap=%lld",
+                         (long long)m, (long long)cap);
+    return MSM_OK;
+}
+
+}  // namespace
+
+extern "C" msm_status msm_enumerate_pairs(msm_ctx* ctx, const uint64_t* S, int64_t n, int32_t ell,
+                                          int32_t k, int32_t h, uint32_t* pairs, int64_t cap,
+                                          int64_t* m_out, void* stream)
+{
+    if (!ctx) return msm::fail(nullptr, MSM_E_INVALID, "msm_enumerate_pairs: ctx is NULL");
+    ctx->err.clear();
+    if (!m_out) return msm::fail(ctx, MSM_E_INVALID, "msm_enumerate_pairs: m_out is NULL");
+    *m_out = 0;
+    if (n < 0 || n > 0xFFFFFFFFll)
+        return msm::fail(ctx, MSM_E_INVALID, "msm_enumerate_pairs: n=%lld out of range", (long long)n);
+    if (ell < 1 || ell > 256)
+        return msm::fail(ctx, MSM_E_INVALID, "msm_enumerate_pairs: ell=%d not in [1, 256]", ell);
+    if (h < 0 || k <= h || k > ell)
+        return msm::fail(ctx, MSM_E_INVALID, "msm_enumerate_pairs: need 0 <= h < k <= ell (k=%d, h=%d)", k, h);
+    if (k > MAXK)
+        return msm::fail(ctx, MSM_E_UNSUPPORTED, "msm_enumerate_pairs: k=%d above %d", k, MAXK);
+    if (binom(k, h) > 65536)
+        return msm::fail(ctx, MSM_E_UNSUPPORTED, "msm_enumerate_pairs: C(%d, %d) combinations above 65536", k, h);
+    if (cap < 0) return msm::fail(ctx, MSM_E_INVALID, "msm_enumerate_pairs: cap < 0");
+    if (cap > 0 && !pairs) return msm::fail(ctx, MSM_E_INVALID, "msm_enumerate_pairs: pairs is NULL with cap > 0");
+    if (pairs && (reinterpret_cast<uintptr_t>(pairs) & 7))
+        return msm::fail(ctx, MSM_E_INVALID, "msm_enumerate_pairs: pairs must be 8-byte aligned");
+    if (n < 2) return MSM_OK;
+    if (!S) return msm::fail(ctx, MSM_E_INVALID, "msm_enumerate_pairs: S is NULL");
+    msm_status st = msm::use_device(ctx);
+    if (st != MSM_OK) return st;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    switch ((ell + 63) / 64) {
+        case 1: return run_enumerate<1>(ctx, S, n, ell, k, h, pairs, cap, m_out, s);
+        case 2: return run_enumerate<2>(ctx, S, n, ell, k, h, pairs, cap, m_out, s);
+        case 3: return run_enumerate<3>(ctx, S, n, ell, k, h, pairs, cap, m_out, s);
+        default: return run_enumerate<4>(ctx, S, n, ell, k, h, pairs, cap, m_out, s);
+    }
+}

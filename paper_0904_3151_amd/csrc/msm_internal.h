@@ -1,0 +1,130 @@
+// Internal declarations of libmsm: the context, error helpers and the
+// device helpers shared by the kernels. Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstddef>
+#include <cstdint>
+#include <cstdio>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "msm.h"
+
+struct msm_ctx {
+    int device = 0;
+    int num_cu = 256;
+    std::string err;
+    // Grow-only device scratch shared by the calls made through the context.
+    void* scratch = nullptr;
+    size_t scratch_bytes = 0;
+    // Pinned host words used to read counters back from the device.
+    uint64_t* host_words = nullptr;
+    // Per-kernel timing: a pair of HIP events around every launch while on.
+    bool prof = false;
+    struct Pending {
+        const char* name;
+        hipEvent_t a, b;
+    };
+    std::vector<hipEvent_t> event_pool;
+    std::vector<Pending> pending;
+    std::map<std::string, std::pair<int64_t, double>> prof_acc;  // launches, ms
+};
+
+namespace msm {
+
+msm_status fail(msm_ctx* ctx, msm_status st, const char* fmt, ...);
+msm_status hip_fail(msm_ctx* ctx, hipError_t e, const char* what);
+// Make the device of ctx current.
+msm_status use_device(msm_ctx* ctx);
+// Device scratch of at least `bytes` (256-byte aligned). Synchronises
+// `stream` before replacing a smaller buffer.
+msm_status scratch(msm_ctx* ctx, size_t bytes, hipStream_t stream, void** out);
+
+// Records a HIP event before and after the launches in its scope, on the
+// launch stream, when profiling is on.
+class KernelTimer {
+public:
+    KernelTimer(msm_ctx* ctx, hipStream_t s, const char* name);
+    ~KernelTimer();
+
+private:
+    msm_ctx* ctx_;
+    hipStream_t s_;
+    const char* name_;
+    hipEvent_t a_ = nullptr;
+};
+
+// Resolves recorded events into per-kernel totals (waits for them).
+msm_status profile_collect(msm_ctx* ctx);
+
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Carves consecutive 256-byte-aligned pieces out of one scratch buffer.
+struct Carver {
+    size_t off = 0;
+    char* base = nullptr;
+    template <class T>
+    T* take(size_t count) {
+        off = align_up(off, 256);
+        T* p = reinterpret_cast<T*>(base ? base + off : nullptr);
+        off += count * sizeof(T);
+        return p;
+    }
+};
+
+#define MSM_HIP(ctx, call)                                              \
+    do {                                                                \
+        hipError_t e_ = (call);                                         \
+        if (e_ != hipSuccess) return ::msm::hip_fail((ctx), e_, #call); \
+    } while (0)
+
+// ----------------------------------------------------------------------
+// Device helpers
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint64_t lanemask_lt()
+{
+    const int l = __lane_id();
+    return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+// Inclusive prefix sum across the 64 lanes of a wave.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v)
+{
+    const int l = __lane_id();
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t t = __shfl_up(v, o, 64);
+        if (l >= o) v += t;
+    }
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Appends the calling lanes' `ok` results to a global list: one atomic per
+// wave, slots in lane order. Must be reached by every lane of the wave.
+// Returns this lane's slot (meaningful only where ok).
+__device__ __forceinline__ unsigned long long wave_append(bool ok, unsigned long long* counter)
+{
+    const uint64_t mask = __ballot(ok);
+    unsigned long long base = 0;
+    if (mask) {
+        const int leader = __builtin_ctzll(mask);
+        if (__lane_id() == leader) base = atomicAdd(counter, (unsigned long long)__popcll(mask));
+        base = __shfl(base, leader, 64);
+    }
+    return base + (unsigned long long)__popcll(mask & lanemask_lt());
+}
+
+}  // namespace msm

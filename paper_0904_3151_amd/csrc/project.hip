@@ -1,0 +1,204 @@
+// Random-projection LSH (Section 3.2, eq. (3)) on the gfx950 matrix cores.
+//
+// z = X R is computed with v_mfma_f32_16x16x4_f32 (FP32 products, FP32
+// accumulation); bit c of string i is 1 iff z_ic > 0. The sign test and the
+// packing into 64-bit words happen in registers: one wave ballot per
+// accumulator register turns 64 comparisons into a scalar mask, so z never
+// reaches memory.
+//
+// Work split: a workgroup of 4 waves owns tiles of 4 * RB * 16 rows and all
+// ell columns (ell <= 256, in NCB blocks of 16). R is staged in LDS in the
+// exact register layout of the MFMA B operand (one 16-byte read per lane per
+// 16-deep K chunk); workgroups are persistent, so R is staged once per
+// workgroup when it fits in 64 KB and once per row tile otherwise.
+//
+// K-order trick: in a 16-deep chunk lane l loads the four consecutive
+// values X[row][k0 + 4g .. k0 + 4g + 3] (g = l / 16) with one 16-byte load,
+// and MFMA j (j = 0..3) consumes component j. The MFMA's internal k index g
+// therefore stands for the true index k0 + 4g + j, and the B operand in LDS
+// is laid out with the same mapping, so the chunk's sum covers all 16 k.
+#include "msm_internal.h"
+
+namespace {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr int PJ_THREADS = 256;
+constexpr int PJ_WAVES = PJ_THREADS / 64;
+constexpr int PJ_LDS_BYTES = 65536;
+
+template <int NCB, int RB>
+__global__ __launch_bounds__(PJ_THREADS) void k_project_f32(
+    const float* __restrict__ X, int64_t n, int d, int64_t ldx, const float* __restrict__ R,
+    int ell, uint64_t* __restrict__ S, int W, int kt_rows, int vec4)
+{
+    extern __shared__ floatx4 Rl[];  // [kt_rows / 16][NCB][64]
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int g = lane >> 4;
+    const int r16 = lane & 15;
+    constexpr int ROWS_PER_TILE = PJ_WAVES * RB * 16;
+    const int64_t ntiles = (n + ROWS_PER_TILE - 1) / ROWS_PER_TILE;
+    const int nkt = (d + kt_rows - 1) / kt_rows;
+    const int kt_chunks = kt_rows / 16;
+
+    // Rl[(kc * NCB + cb) * 64 + l][j] = R[k0 + 16 kc + 4 (l / 16) + j][16 cb + l % 16]
+    auto stage = [&](int k0) {
+        const int total = kt_chunks * NCB * 64;
+        for (int e = threadIdx.x; e < total; e += PJ_THREADS) {
+            const int l = e & 63;
+            const int cb = (e >> 6) % NCB;
+            const int kc = (e >> 6) / NCB;
+            const int c = cb * 16 + (l & 15);
+            const int kb = k0 + kc * 16 + 4 * (l >> 4);
+            floatx4 v;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int k = kb + j;
+                v[j] = (k < d && c < ell) ? R[(int64_t)k * ell + c] : 0.0f;
+            }
+            Rl[e] = v;
+        }
+    };
+
+    if (nkt == 1) {
+        stage(0);
+        __syncthreads();
+    }
+
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int64_t row_w = tile * ROWS_PER_TILE + (int64_t)wave * RB * 16;
+        floatx4 acc[RB][NCB];
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) acc[rb][cb] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+        for (int kt = 0; kt < nkt; ++kt) {
+            const int k0 = kt * kt_rows;
+            if (nkt > 1) {
+                __syncthreads();
+                stage(k0);
+                __syncthreads();
+            }
+            const int kcn = min(kt_chunks, (d - k0 + 15) / 16);
+            for (int kc = 0; kc < kcn; ++kc) {
+                const int kbase = k0 + kc * 16 + 4 * g;
+                floatx4 a[RB];
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb) {
+                    const int64_t row = row_w + rb * 16 + r16;
+                    floatx4 v = floatx4{0.f, 0.f, 0.f, 0.f};
+                    if (row < n) {
+                        const float* xr = X + row * ldx;
+                        if (vec4 && kbase + 3 < d) {
+                            v = *reinterpret_cast<const floatx4*>(xr + kbase);
+                        } else {
+#pragma unroll
+                            for (int j = 0; j < 4; ++j)
+                                if (kbase + j < d) v[j] = xr[kbase + j];
+                        }
+                    }
+                    a[rb] = v;
+                }
+                floatx4 b[NCB];
+#pragma unroll
+                for (int cb = 0; cb < NCB; ++cb) b[cb] = Rl[(kc * NCB + cb) * 64 + lane];
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+#pragma unroll
+                    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                        for (int cb = 0; cb < NCB; ++cb)
+                            acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb][j], b[cb][j],
+                                                                               acc[rb][cb], 0, 0, 0);
+            }
+        }
+
+        // Epilogue. Accumulator register i of lane l holds z for row
+        // 4 (l / 16) + i and column l % 16 of the 16 x 16 block, so
+        // ballot(acc[i] > 0) gives, in bits 16 q .. 16 q + 15, the 16 signs
+        // of row 4 q + i. Lane l then assembles word l / 16 of row l % 16.
+        const int orow = lane & 15;
+        const int oword = lane >> 4;
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+            uint64_t word = 0;
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) {
+                const uint64_t m0 = __ballot(acc[rb][cb][0] > 0.0f);
+                const uint64_t m1 = __ballot(acc[rb][cb][1] > 0.0f);
+                const uint64_t m2 = __ballot(acc[rb][cb][2] > 0.0f);
+                const uint64_t m3 = __ballot(acc[rb][cb][3] > 0.0f);
+                const int i = orow & 3;
+                const uint64_t mi = i == 0 ? m0 : (i == 1 ? m1 : (i == 2 ? m2 : m3));
+                const uint64_t bits = (mi >> (16 * (orow >> 2))) & 0xFFFFull;
+                if ((cb >> 2) == oword) word |= bits << (16 * (cb & 3));
+            }
+            const int64_t row = row_w + rb * 16 + orow;
+            if (row < n && oword < W) S[row * W + oword] = word;
+        }
+    }
+}
+
+template <int NCB>
+msm_status launch_project(msm_ctx* ctx, const float* X, int64_t n, int d, int64_t ldx,
+                          const float* R, int ell, uint64_t* S, hipStream_t stream)
+{
+    constexpr int RB = NCB <= 4 ? 4 : (NCB <= 8 ? 2 : 1);
+    constexpr int ROWS_PER_TILE = PJ_WAVES * RB * 16;
+    const int W = (ell + 63) / 64;
+    const int dpad = (d + 15) / 16 * 16;
+    const int max_chunks = PJ_LDS_BYTES / (NCB * 64 * 16);
+    const int kt_rows = min(dpad, max_chunks * 16);
+    const size_t lds = (size_t)(kt_rows / 16) * NCB * 64 * sizeof(floatx4);
+    const int vec4 = ((reinterpret_cast<uintptr_t>(X) & 15) == 0) && (ldx % 4 == 0);
+    const int64_t ntiles = (n + ROWS_PER_TILE - 1) / ROWS_PER_TILE;
+    const int64_t grid = ntiles < (int64_t)ctx->num_cu * 2 ? ntiles : (int64_t)ctx->num_cu * 2;
+    {
+        msm::KernelTimer kt(ctx, stream, "k_project_f32");
+        hipLaunchKernelGGL((k_project_f32<NCB, RB>), dim3((unsigned)grid), dim3(PJ_THREADS), lds, stream,
+                           X, n, d, ldx, R, ell, S, W, kt_rows, vec4);
+    }
+    MSM_HIP(ctx, hipGetLastError());
+    return MSM_OK;
+}
+
+}  // namespace
+
+extern "C" msm_status msm_project(msm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
+                                  const float* R, int32_t ell, uint64_t* S, void* stream)
+{
+    if (!ctx) return msm::fail(nullptr, MSM_E_INVALID, "msm_project: ctx is NULL");
+    ctx->err.clear();
+    if (n < 0 || n > 0xFFFFFFFFll)
+        return msm::fail(ctx, MSM_E_INVALID, "msm_project: n=%lld out of range", (long long)n);
+    if (d < 1 || ldx < d)
+        return msm::fail(ctx, MSM_E_INVALID, "msm_project: need d >= 1 and ldx >= d (d=%d, ldx=%lld)",
+                         d, (long long)ldx);
+    if (ell < 1 || ell > 256)
+        return msm::fail(ctx, MSM_E_INVALID, "msm_project: ell=%d not in [1, 256]", ell);
+    if (n == 0) return MSM_OK;
+    if (!X || !R || !S) return msm::fail(ctx, MSM_E_INVALID, "msm_project: NULL X, R or S");
+    msm_status st = msm::use_device(ctx);
+    if (st != MSM_OK) return st;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    switch ((ell + 15) / 16) {
+        case 1: return launch_project<1>(ctx, X, n, d, ldx, R, ell, S, s);
+        case 2: return launch_project<2>(ctx, X, n, d, ldx, R, ell, S, s);
+        case 3: return launch_project<3>(ctx, X, n, d, ldx, R, ell, S, s);
+        case 4: return launch_project<4>(ctx, X, n, d, ldx, R, ell, S, s);
+        case 5: return launch_project<5>(ctx, X, n, d, ldx, R, ell, S, s);
+        case 6: return launch_project<6>(ctx, X, n, d, ldx, R, ell, S, s);
+        case 7: return launch_project<7>(ctx, X, n, d, ldx, R, ell, S, s);
+        case 8: return launch_project<8>(ctx, X, n, d, ldx, R, ell, S, s);
+        case 9: return launch_project<9>(ctx, X, n, d, ldx, R, ell, S, s);
+        case 10: return launch_project<10>(ctx, X, n, d, ldx, R, ell, S, s);
+        case 11: return launch_project<11>(ctx, X, n, d, ldx, R, ell, S, s);
+        case 12: return launch_project<12>(ctx, X, n, d, ldx, R, ell, S, s);
+        case 13: return launch_project<13>(ctx, X, n, d, ldx, R, ell, S, s);
+        case 14: return launch_project<14>(ctx, X, n, d, ldx, R, ell, S, s);
+        case 15: return launch_project<15>(ctx, X, n, d, ldx, R, ell, S, s);
+        default: return launch_project<16>(ctx, X, n, d, ldx, R, ell, S, s);
+    }
+}

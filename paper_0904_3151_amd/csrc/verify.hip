@@ -1,0 +1,171 @@
+// Distance verification of candidate pairs (Section 4.1, Definition 1.1).
+//
+// A team of 16 lanes handles one pair: each lane reads consecutive 16-byte
+// pieces of x_i and x_j (a team covers 256 contiguous bytes per row per
+// step), accumulates in FP32, and the team reduces with lane shuffles. The
+// team leaders then append the kept pairs with one atomic per wave.
+#include "msm_internal.h"
+
+namespace {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr int VF_THREADS = 256;
+constexpr int VF_TEAM = 16;
+
+template <int METRIC, bool VEC4>
+__global__ __launch_bounds__(VF_THREADS) void k_verify(const float* __restrict__ X, int64_t n, int d,
+                                                       int64_t ldx, const uint32_t* __restrict__ pairs,
+                                                       int64_t m, float eps, uint32_t* __restrict__ out,
+                                                       unsigned long long cap, unsigned long long* counter,
+                                                       uint32_t* bad)
+{
+    const int tl = threadIdx.x & (VF_TEAM - 1);
+    const int64_t team = ((int64_t)blockIdx.x * VF_THREADS + threadIdx.x) / VF_TEAM;
+    const int64_t nteams = ((int64_t)gridDim.x * VF_THREADS) / VF_TEAM;
+    // every lane runs the same number of iterations so wave_append is reached uniformly
+    const int64_t rounds = (m + nteams - 1) / nteams;
+    for (int64_t it = 0; it < rounds; ++it) {
+        const int64_t q = team + it * nteams;
+        bool live = q < m;
+        uint32_t i = 0, j = 0;
+        if (live) {
+            const uint2 pr = *reinterpret_cast<const uint2*>(pairs + 2 * q);
+            i = pr.x;
+            j = pr.y;
+            if ((int64_t)i >= n || (int64_t)j >= n) {
+                if (tl == 0) atomicAdd(bad, 1u);
+                live = false;
+            }
+        }
+        float a0 = 0.f, a1 = 0.f, a2 = 0.f;
+        if (live) {
+            const float* xi = X + (int64_t)i * ldx;
+            const float* xj = X + (int64_t)j * ldx;
+            if (VEC4) {
+                for (int t = tl * 4; t < d; t += VF_TEAM * 4) {
+                    const floatx4 u = *reinterpret_cast<const floatx4*>(xi + t);
+                    const floatx4 v = *reinterpret_cast<const floatx4*>(xj + t);
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        if (METRIC == MSM_EUCLIDEAN) {
+                            const float e = u[c] - v[c];
+                            a0 = fmaf(e, e, a0);
+                        } else {
+                            a0 = fmaf(u[c], v[c], a0);
+                            a1 = fmaf(u[c], u[c], a1);
+                            a2 = fmaf(v[c], v[c], a2);
+                        }
+                    }
+                }
+            } else {
+                for (int t = tl; t < d; t += VF_TEAM) {
+                    const float u = xi[t], v = xj[t];
+                    if (METRIC == MSM_EUCLIDEAN) {
+                        const float e = u - v;
+                        a0 = fmaf(e, e, a0);
+                    } else {
+                        a0 = fmaf(u, v, a0);
+                        a1 = fmaf(u, u, a1);
+                        a2 = fmaf(v, v, a2);
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int o = VF_TEAM / 2; o > 0; o >>= 1) {
+            a0 += __shfl_xor(a0, o, 64);
+            if (METRIC == MSM_COSINE) {
+                a1 += __shfl_xor(a1, o, 64);
+                a2 += __shfl_xor(a2, o, 64);
+            }
+        }
+        bool keep = false;
+        if (live && tl == 0) {
+            if (METRIC == MSM_EUCLIDEAN) {
+                keep = a0 <= eps * eps;
+            } else {
+                const float dist = (a1 == 0.f || a2 == 0.f) ? 1.0f : 1.0f - a0 / (sqrtf(a1) * sqrtf(a2));
+                keep = dist <= eps;
+            }
+        }
+        const unsigned long long slot = msm::wave_append(keep, counter);
+        if (keep && slot < cap) *reinterpret_cast<uint2*>(out + 2 * slot) = make_uint2(i, j);
+    }
+}
+
+__global__ void k_zero_words(unsigned long long* a, int n)
+{
+    const int i = threadIdx.x;
+    if (i < n) a[i] = 0ull;
+}
+
+template <int METRIC>
+void launch(bool vec4, dim3 grid, hipStream_t s, const float* X, int64_t n, int d, int64_t ldx,
+            const uint32_t* pairs, int64_t m, float eps, uint32_t* out, int64_t cap,
+            unsigned long long* counter, uint32_t* bad)
+{
+    if (vec4)
+        hipLaunchKernelGGL((k_verify<METRIC, true>), grid, dim3(VF_THREADS), 0, s, X, n, d, ldx, pairs, m, eps,
+                           out, (unsigned long long)cap, counter, bad);
+    else
+        hipLaunchKernelGGL((k_verify<METRIC, false>), grid, dim3(VF_THREADS), 0, s, X, n, d, ldx, pairs, m, eps,
+                           out, (unsigned long long)cap, counter, bad);
+}
+
+}  // namespace
+
+extern "C" msm_status msm_verify(msm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
+                                 const uint32_t* pairs, int64_t m, int32_t metric, float eps,
+                                 uint32_t* out, int64_t cap, int64_t* m_out, void* stream)
+{
+    if (!ctx) return msm::fail(nullptr, MSM_E_INVALID, "msm_verify: ctx is NULL");
+    ctx->err.clear();
+    if (!m_out) return msm::fail(ctx, MSM_E_INVALID, "msm_verify: m_out is NULL");
+    *m_out = 0;
+    if (n < 0 || n > 0xFFFFFFFFll || d < 1 || ldx < d || m < 0 || cap < 0)
+        return msm::fail(ctx, MSM_E_INVALID, "msm_verify: sizes out of range");
+    if (metric != MSM_EUCLIDEAN && metric != MSM_COSINE)
+        return msm::fail(ctx, MSM_E_INVALID, "msm_verify: unknown metric %d", metric);
+    if (!(eps >= 0.0f) || eps == __builtin_inff())
+        return msm::fail(ctx, MSM_E_INVALID, "msm_verify: eps must be finite and >= 0");
+    if (m == 0) return MSM_OK;
+    if (!X || !pairs) return msm::fail(ctx, MSM_E_INVALID, "msm_verify: NULL X or pairs");
+    if (cap > 0 && !out) return msm::fail(ctx, MSM_E_INVALID, "msm_verify: out is NULL with cap > 0");
+    if ((reinterpret_cast<uintptr_t>(pairs) & 7) || (out && (reinterpret_cast<uintptr_t>(out) & 7)))
+        return msm::fail(ctx, MSM_E_INVALID, "msm_verify: pair buffers must be 8-byte aligned");
+    msm_status st = msm::use_device(ctx);
+    if (st != MSM_OK) return st;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    void* scr = nullptr;
+    st = msm::scratch(ctx, 256, s, &scr);
+    if (st != MSM_OK) return st;
+    unsigned long long* counter = static_cast<unsigned long long*>(scr);
+    uint32_t* bad = reinterpret_cast<uint32_t*>(counter + 1);
+    hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(64), 0, s, counter, 2);
+    const bool vec4 = ((reinterpret_cast<uintptr_t>(X) & 15) == 0) && (ldx % 4 == 0) && (d % 4 == 0);
+    const int64_t teams_per_block = VF_THREADS / VF_TEAM;
+    int64_t blocks = (m + teams_per_block - 1) / teams_per_block;
+    const int64_t max_blocks = (int64_t)ctx->num_cu * 16;
+    if (blocks > max_blocks) blocks = max_blocks;
+    {
+        msm::KernelTimer kt(ctx, s, "k_verify");
+        if (metric == MSM_EUCLIDEAN)
+            launch<MSM_EUCLIDEAN>(vec4, dim3((unsigned)blocks), s, X, n, d, ldx, pairs, m, eps, out, cap, counter,
+                                  bad);
+        else
+            launch<MSM_COSINE>(vec4, dim3((unsigned)blocks), s, X, n, d, ldx, pairs, m, eps, out, cap, counter, bad);
+    }
+    MSM_HIP(ctx, hipGetLastError());
+    MSM_HIP(ctx, hipMemcpyAsync(ctx->host_words, counter, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    MSM_HIP(ctx, hipStreamSynchronize(s));
+    const int64_t kept = (int64_t)ctx->host_words[0];
+    const uint32_t nbad = (uint32_t)(ctx->host_words[1] & 0xFFFFFFFFull);
+    if (nbad)
+        return msm::fail(ctx, MSM_E_INVALID, "msm_verify: %u pairs have an index >= n", nbad);
+    *m_out = kept;
+    if (kept > cap && !(out == nullptr && cap == 0))
+        return msm::fail(ctx, MSM_E_CAPACITY, "msm_verify: %lld pairs do not fit in cap=%lld", (long long)kept,
+                         (long long)cap);
+    return MSM_OK;
+}

@@ -1,0 +1,288 @@
+"""Thin ctypes binding of libmsm (C ABI in include/msm.h).
+
+Each ``msm_*`` function here marshals torch tensors into the C call of the
+same name: device pointers, sizes and the current HIP stream. Every step of
+the computation runs in the library's HIP kernels; PyTorch only provides
+device memory and streams.
+
+Importing this module loads ``libmsm.so`` and raises ImportError if it has
+not been built (``python -m paper_0904_3151_amd.build``). There is no CPU
+fallback.
+
+Tensor conventions: X is float32 (n, d) with unit column stride; R is
+float32 (d, ell) contiguous; strings S are int64 (n, W) holding the uint64
+words; pair lists are int32 (m, 2) holding uint32 indices (i, j), i < j.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmsm.so")
+
+MSM_OK = 0
+MSM_E_INVALID = -1
+MSM_E_CAPACITY = -2
+MSM_E_UNSUPPORTED = -3
+MSM_E_NOMEM = -4
+MSM_E_HIP = -5
+
+EUCLIDEAN = 0
+COSINE = 1
+METRICS = {"euclidean": EUCLIDEAN, "cosine": COSINE}
+
+EXPORTS = ("msm_version", "msm_create", "msm_destroy", "msm_last_error",
+           "msm_project", "msm_enumerate_pairs", "msm_verify", "msm_bruteforce_eps",
+           "msm_profile_enable", "msm_profile_reset", "msm_profile_read")
+
+
+class KernelTime(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double)]
+
+
+class MSMError(RuntimeError):
+    def __init__(self, status: int, message: str, required: int | None = None):
+        super().__init__(f"[status {status}] {message}")
+        self.status = status
+        self.required = required
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_0904_3151_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    i64, i32, vp = ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p
+    lib.msm_version.argtypes = []
+    lib.msm_version.restype = i32
+    lib.msm_create.argtypes = [i32, ctypes.POINTER(vp)]
+    lib.msm_create.restype = i32
+    lib.msm_destroy.argtypes = [vp]
+    lib.msm_destroy.restype = None
+    lib.msm_last_error.argtypes = [vp]
+    lib.msm_last_error.restype = ctypes.c_char_p
+    lib.msm_project.argtypes = [vp, vp, i64, i32, i64, vp, i32, vp, vp]
+    lib.msm_project.restype = i32
+    lib.msm_enumerate_pairs.argtypes = [vp, vp, i64, i32, i32, i32, vp, i64, ctypes.POINTER(i64), vp]
+    lib.msm_enumerate_pairs.restype = i32
+    lib.msm_verify.argtypes = [vp, vp, i64, i32, i64, vp, i64, i32, ctypes.c_float, vp, i64,
+                               ctypes.POINTER(i64), vp]
+    lib.msm_verify.restype = i32
+    lib.msm_bruteforce_eps.argtypes = [vp, vp, i64, i32, i64, i32, ctypes.c_float, vp, i64,
+                                       ctypes.POINTER(i64), vp]
+    lib.msm_bruteforce_eps.restype = i32
+    lib.msm_profile_enable.argtypes = [vp, i32]
+    lib.msm_profile_enable.restype = i32
+    lib.msm_profile_reset.argtypes = [vp]
+    lib.msm_profile_reset.restype = i32
+    lib.msm_profile_read.argtypes = [vp, ctypes.POINTER(KernelTime), i32]
+    lib.msm_profile_read.restype = i32
+    return lib
+
+
+_lib = _load()
+
+
+def lib():
+    return _lib
+
+
+def msm_version() -> int:
+    return int(_lib.msm_version())
+
+
+class Context:
+    """Owns an msm_ctx (device scratch) on one HIP device."""
+
+    def __init__(self, device: int = 0):
+        h = ctypes.c_void_p()
+        st = _lib.msm_create(int(device), ctypes.byref(h))
+        if st != MSM_OK:
+            raise MSMError(st, _lib.msm_last_error(None).decode())
+        self._h = h
+        self.device = int(device)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def last_error(self) -> str:
+        return _lib.msm_last_error(self._h).decode()
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.msm_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def _check(ctx: Context, st: int, required: int | None = None):
+    if st != MSM_OK:
+        raise MSMError(st, ctx.last_error(), required)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, torch.cuda.Stream):
+        return ctypes.c_void_p(stream.cuda_stream)
+    return ctypes.c_void_p(int(stream))
+
+
+def _words(ell: int) -> int:
+    return (ell + 63) // 64
+
+
+def msm_project(ctx: Context, X: torch.Tensor, R: torch.Tensor, S: torch.Tensor | None = None,
+                stream=None) -> torch.Tensor:
+    """Sign strings of X @ R (eq. (3)); returns S as int64 (n, W)."""
+    assert X.dtype == torch.float32 and X.dim() == 2 and X.stride(1) == 1 and X.is_cuda
+    assert R.dtype == torch.float32 and R.dim() == 2 and R.is_contiguous() and R.is_cuda
+    n, d = X.shape
+    ell = R.shape[1]
+    assert R.shape[0] == d
+    if S is None:
+        S = torch.empty((n, _words(ell)), dtype=torch.int64, device=X.device)
+    assert S.dtype == torch.int64 and S.is_contiguous() and S.shape == (n, _words(ell))
+    st = _lib.msm_project(ctx.handle, _ptr(X), n, d, X.stride(0) if n > 0 else d, _ptr(R), ell,
+                          _ptr(S), _stream(stream))
+    _check(ctx, st)
+    return S
+
+
+def msm_enumerate_pairs(ctx: Context, S: torch.Tensor, ell: int, k: int, h: int,
+                        pairs: torch.Tensor | None = None, cap: int | None = None, stream=None):
+    """Pairs within Hamming distance h (Sections 2.1-2.2).
+
+    Writes into ``pairs`` (int32, (cap, 2)) and returns (pairs[:m], m). Raises
+    MSMError with status MSM_E_CAPACITY (``.required`` = m) if it did not fit.
+    ``pairs=None, cap=0`` is a count-only call returning (None, m).
+    """
+    assert S.dtype == torch.int64 and S.dim() == 2 and S.is_contiguous() and S.is_cuda
+    n = S.shape[0]
+    assert S.shape[1] == _words(ell)
+    if pairs is None:
+        cap = 0 if cap is None else int(cap)
+        if cap > 0:
+            pairs = torch.empty((cap, 2), dtype=torch.int32, device=S.device)
+    else:
+        assert pairs.dtype == torch.int32 and pairs.is_contiguous() and pairs.dim() == 2
+        cap = pairs.shape[0] if cap is None else int(cap)
+    m = ctypes.c_int64(0)
+    st = _lib.msm_enumerate_pairs(ctx.handle, _ptr(S), n, int(ell), int(k), int(h), _ptr(pairs), cap,
+                                  ctypes.byref(m), _stream(stream))
+    _check(ctx, st, m.value)
+    return (pairs[: m.value] if pairs is not None else None), m.value
+
+
+def msm_verify(ctx: Context, X: torch.Tensor, pairs: torch.Tensor, metric, eps: float,
+               out: torch.Tensor | None = None, cap: int | None = None, stream=None):
+    """Pairs of ``pairs`` whose distance is at most eps (Section 4.1).
+
+    Returns (out[:kept], kept); raises MSMError on failure (MSM_E_CAPACITY with
+    ``.required`` when ``out`` is too small).
+    """
+    if isinstance(metric, str):
+        metric = METRICS[metric]
+    assert X.dtype == torch.float32 and X.dim() == 2 and X.stride(1) == 1 and X.is_cuda
+    assert pairs.dtype == torch.int32 and pairs.is_contiguous()
+    pairs = pairs.reshape(-1, 2)
+    n, d = X.shape
+    m = pairs.shape[0]
+    if out is None:
+        cap = m if cap is None else int(cap)
+        out = torch.empty((max(cap, 1), 2), dtype=torch.int32, device=X.device)
+    else:
+        assert out.dtype == torch.int32 and out.is_contiguous()
+        cap = out.shape[0] if cap is None else int(cap)
+    kept = ctypes.c_int64(0)
+    st = _lib.msm_verify(ctx.handle, _ptr(X), n, d, X.stride(0) if n > 0 else d, _ptr(pairs), m,
+                         int(metric), float(eps), _ptr(out), cap, ctypes.byref(kept), _stream(stream))
+    _check(ctx, st, kept.value)
+    return out[: kept.value], kept.value
+
+
+def msm_bruteforce_eps(ctx: Context, X: torch.Tensor, metric, eps: float, out: torch.Tensor | None = None,
+                       cap: int | None = None, stream=None):
+    """All pairs with distance <= eps by exhaustive search (Definition 1.1).
+
+    Returns (out[:m], m); ``out=None, cap=0`` counts only.
+    """
+    if isinstance(metric, str):
+        metric = METRICS[metric]
+    assert X.dtype == torch.float32 and X.dim() == 2 and X.stride(1) == 1 and X.is_cuda
+    n, d = X.shape
+    if out is None:
+        cap = 0 if cap is None else int(cap)
+        if cap > 0:
+            out = torch.empty((cap, 2), dtype=torch.int32, device=X.device)
+    else:
+        assert out.dtype == torch.int32 and out.is_contiguous()
+        cap = out.shape[0] if cap is None else int(cap)
+    m = ctypes.c_int64(0)
+    st = _lib.msm_bruteforce_eps(ctx.handle, _ptr(X), n, d, X.stride(0) if n > 0 else d, int(metric), float(eps),
+                                 _ptr(out), cap, ctypes.byref(m), _stream(stream))
+    _check(ctx, st, m.value)
+    return (out[: m.value] if out is not None else None), m.value
+
+
+def bruteforce_eps(ctx: Context, X: torch.Tensor, metric, eps: float, cap_hint: int = 1 << 20, stream=None):
+    """msm_bruteforce_eps with an output buffer grown on demand."""
+    cap = max(1, int(cap_hint))
+    while True:
+        try:
+            return msm_bruteforce_eps(ctx, X, metric, eps, cap=cap, stream=stream)
+        except MSMError as e:
+            if e.status != MSM_E_CAPACITY:
+                raise
+            cap = int(e.required)
+
+
+def msm_profile_enable(ctx: Context, enable: bool = True):
+    _check(ctx, _lib.msm_profile_enable(ctx.handle, int(bool(enable))))
+
+
+def msm_profile_reset(ctx: Context):
+    _check(ctx, _lib.msm_profile_reset(ctx.handle))
+
+
+def msm_profile_read(ctx: Context) -> dict:
+    """{kernel name: (launches, total_ms)} of the event timings so far."""
+    cnt = _lib.msm_profile_read(ctx.handle, None, 0)
+    if cnt < 0:
+        raise MSMError(MSM_E_HIP, ctx.last_error())
+    buf = (KernelTime * max(cnt, 1))()
+    cnt = _lib.msm_profile_read(ctx.handle, buf, cnt)
+    if cnt < 0:
+        raise MSMError(MSM_E_HIP, ctx.last_error())
+    return {buf[i].name.decode(): (int(buf[i].launches), float(buf[i].total_ms)) for i in range(cnt)}
+
+
+def enumerate_pairs(ctx: Context, S: torch.Tensor, ell: int, k: int, h: int, cap_hint: int = 1 << 20,
+                    stream=None):
+    """msm_enumerate_pairs with an output buffer that is grown on demand."""
+    cap = max(1, int(cap_hint))
+    while True:
+        try:
+            return msm_enumerate_pairs(ctx, S, ell, k, h, cap=cap, stream=stream)
+        except MSMError as e:
+            if e.status != MSM_E_CAPACITY:
+                raise
+            cap = int(e.required)

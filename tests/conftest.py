@@ -17,3 +17,24 @@ def pytest_configure(config):
 def oracle_lib():
     from oracle import oracle
     return oracle
+
+
+@pytest.fixture(scope="session")
+def msm():
+    """The ctypes binding; importing it fails loudly if libmsm.so is missing."""
+    from paper_0904_3151_amd import msm as M
+    return M
+
+
+@pytest.fixture(scope="session")
+def ctx(msm):
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    c = msm.Context(0)
+    yield c
+    c.close()
+
+
+def announce(*parts):
+    """Print and flush the case name before a GPU step."""
+    print("[gpu-case]", *parts, flush=True)
