@@ -60,8 +60,9 @@ def cpu_baseline(w, X, R, sample):
     O.verify(Xs, P, O.EUCLIDEAN, float(np.float32(w.eps)))
     t = time.perf_counter() - t0
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+    what = "all" if sample == w.n else f"first {sample} of"
     return {"value": sample / t, "unit": "points/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {sample} of {w.n} points (FP64 project + MSM + verify), {t:.1f} s"}
+            "sample": f"{what} {w.n} points, one full step (FP64 project + MSM + verify), {t:.1f} s"}
 
 
 def main():
@@ -70,7 +71,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--sigma-mode", default="coord", choices=["coord", "radius"])
-    ap.add_argument("--cpu-sample", type=int, default=250_000)
+    ap.add_argument("--cpu-sample", type=int, default=0, help="rows for the CPU oracle (0: all)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -145,8 +146,9 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        log(f"cpu baseline on {args.cpu_sample} points")
-        cpu = cpu_baseline(w, X, R, args.cpu_sample)
+        sample = args.cpu_sample if 0 < args.cpu_sample < n else n
+        log(f"cpu baseline on {sample} points")
+        cpu = cpu_baseline(w, X, R, sample)
 
     out = {
         "metric": METRIC,

@@ -47,6 +47,8 @@ constexpr int BK_WAVES = BK_THREADS / 64;
 constexpr int BK_MAXB = 4;                        // 64-element batches per wave
 constexpr int BK_CAP = BK_WAVES * 64 * BK_MAXB;   // largest bucket sorted in LDS
 constexpr int BK_PAIR_CHUNK = 8;                  // consecutive pairs per lane
+constexpr int BK_GROUP = 8;                       // buckets per workgroup
+constexpr int BK_OUT = 2048;                      // staged output pairs per workgroup
 constexpr int BIG_TILE = 256;
 constexpr int MAX_BUCKETS = 8192;
 constexpr int TARGET_BUCKET = 512;
@@ -246,16 +248,6 @@ __device__ __forceinline__ bool pair_ok(const uint64_t* a, const uint64_t* b, co
     return ok;
 }
 
-__device__ __forceinline__ void write_pair(const Params& p, bool ok, unsigned long long slot,
-                                           uint32_t i, uint32_t j)
-{
-    if (ok && slot < p.cap) {
-        const uint32_t lo = i < j ? i : j;
-        const uint32_t hi = i < j ? j : i;
-        *reinterpret_cast<uint2*>(p.pairs + 2 * slot) = make_uint2(lo, hi);
-    }
-}
-
 // Exclusive prefix over values laid out as position = wave*256 + b*64 + lane
 // (the element layout of k_bucket). Returns the block total.
 __device__ __forceinline__ uint32_t scan_wbl(const uint32_t (&v)[BK_MAXB], uint32_t (&ex)[BK_MAXB],
@@ -285,7 +277,7 @@ __device__ __forceinline__ uint32_t scan_wbl(const uint32_t (&v)[BK_MAXB], uint3
 }
 
 // -------------------------------------------------------------------------
-// 2. one bucket per workgroup
+// 2. buckets, BK_GROUP consecutive ones per workgroup
 
 template <int W>
 __global__ __launch_bounds__(BK_THREADS) void k_bucket(Params p)
@@ -299,21 +291,11 @@ __global__ __launch_bounds__(BK_THREADS) void k_bucket(Params p)
     __shared__ uint32_t runP[BK_CAP + 1];
     __shared__ uint64_t bmL[MAXK * W];
     __shared__ uint32_t tmp[BK_WAVES];
+    __shared__ uint2 obuf[BK_OUT];
+    __shared__ uint32_t ocnt;
+    __shared__ unsigned long long ogb;
 
-    const int bk = blockIdx.x;
     const int cl = blockIdx.y;
-    const uint32_t* base = p.base + (size_t)cl * (p.nb + 1);
-    const uint32_t beg = base[bk];
-    const uint32_t cnt = base[bk + 1] - beg;
-    if (cnt < 2) return;
-    if (cnt > (uint32_t)BK_CAP) {
-        if (threadIdx.x == 0) {
-            const uint32_t o = atomicAdd(p.ovf_count, 1u);
-            p.ovf[o] = Ovf{(uint32_t)cl, beg, cnt, 0u};
-        }
-        return;
-    }
-    const int m = (int)cnt;
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     const Combo* cb = p.combos + cl;
@@ -321,173 +303,194 @@ __global__ __launch_bounds__(BK_THREADS) void k_bucket(Params p)
     load_keep<W>(cb, keep);
     const uint64_t hi = cb->hi;
     for (int e = threadIdx.x; e < p.k * W; e += BK_THREADS) bmL[e] = p.bm[(e / W) * MAXW + (e % W)];
+    if (threadIdx.x == 0) ocnt = 0;
+    msm::PairStager<BK_OUT> out{obuf, &ocnt, &ogb, p.pairs, p.cap, p.counter};
+    const uint32_t* base = p.base + (size_t)cl * (p.nb + 1);
+    const int bk0 = blockIdx.x * BK_GROUP;
+    const int bk1 = min(p.nb, bk0 + BK_GROUP);
 
-    const uint64_t* part = p.part + (size_t)cl * p.n + beg;
-    uint64_t key[BK_MAXB];
-    int pos[BK_MAXB];
-    bool valid[BK_MAXB];
-#pragma unroll
-    for (int b = 0; b < BK_MAXB; ++b) {
-        pos[b] = wave * (64 * BK_MAXB) + b * 64 + lane;
-        valid[b] = pos[b] < m;
-        key[b] = valid[b] ? part[pos[b]] : ~0ull;
-    }
-
-    // Stable LSD radix sort on mix bits [sort_lo, sort_lo + 16): two 8-bit
-    // digits. Lanes with equal digits in a batch of 64 find each other with
-    // eight ballots; ranks follow position order, so each pass is stable.
-#pragma unroll
-    for (int pass = 0; pass < 2; ++pass) {
-        const int sh = 32 + p.sort_lo + 8 * pass;
-        for (int i = lane; i < 256; i += 64) whist[wave][i] = 0;
-        __syncthreads();
-        uint32_t loc[BK_MAXB];
-        uint32_t dg[BK_MAXB];
+    for (int bk = bk0; bk < bk1; ++bk) {
+        __syncthreads();  // the previous bucket's LDS data is no longer read
+        const uint32_t beg = base[bk];
+        const uint32_t cnt = base[bk + 1] - beg;
+        if (cnt < 2) continue;
+        if (cnt > (uint32_t)BK_CAP) {
+            if (threadIdx.x == 0) {
+                const uint32_t o = atomicAdd(p.ovf_count, 1u);
+                p.ovf[o] = Ovf{(uint32_t)cl, beg, cnt, 0u};
+            }
+            continue;
+        }
+        const int m = (int)cnt;
+        const uint64_t* part = p.part + (size_t)cl * p.n + beg;
+        uint64_t key[BK_MAXB];
+        int pos[BK_MAXB];
+        bool valid[BK_MAXB];
 #pragma unroll
         for (int b = 0; b < BK_MAXB; ++b) {
-            dg[b] = (uint32_t)(key[b] >> sh) & 0xFFu;
-            uint64_t peers = __ballot(valid[b]);
-#pragma unroll
-            for (int bit = 0; bit < 8; ++bit) {
-                const bool set = (dg[b] >> bit) & 1u;
-                const uint64_t bb = __ballot(set);
-                peers &= set ? bb : ~bb;
-            }
-            const uint32_t rank = (uint32_t)__popcll(peers & msm::lanemask_lt());
-            uint32_t old = 0;
-            if (valid[b]) old = whist[wave][dg[b]];
-            if (valid[b] && rank == 0) whist[wave][dg[b]] = old + (uint32_t)__popcll(peers);
-            loc[b] = old + rank;
+            pos[b] = wave * (64 * BK_MAXB) + b * 64 + lane;
+            valid[b] = pos[b] < m;
+            key[b] = valid[b] ? part[pos[b]] : ~0ull;
         }
-        __syncthreads();
-        {
-            const int dgt = threadIdx.x;  // BK_THREADS == 256 digits
-            uint32_t s = 0;
+
+        // Stable LSD radix sort on mix bits [sort_lo, sort_lo + 16): two
+        // 8-bit digits. Lanes with equal digits in a batch of 64 find each
+        // other with eight ballots; ranks follow position order, so each
+        // pass is stable.
 #pragma unroll
-            for (int w = 0; w < BK_WAVES; ++w) {
-                const uint32_t v = whist[w][dgt];
-                whist[w][dgt] = s;
-                s += v;
+        for (int pass = 0; pass < 2; ++pass) {
+            const int sh = 32 + p.sort_lo + 8 * pass;
+            for (int i = lane; i < 256; i += 64) whist[wave][i] = 0;
+            __syncthreads();
+            uint32_t loc[BK_MAXB];
+            uint32_t dg[BK_MAXB];
+#pragma unroll
+            for (int b = 0; b < BK_MAXB; ++b) {
+                dg[b] = (uint32_t)(key[b] >> sh) & 0xFFu;
+                uint64_t peers = __ballot(valid[b]);
+#pragma unroll
+                for (int bit = 0; bit < 8; ++bit) {
+                    const bool set = (dg[b] >> bit) & 1u;
+                    const uint64_t bb = __ballot(set);
+                    peers &= set ? bb : ~bb;
+                }
+                const uint32_t rank = (uint32_t)__popcll(peers & msm::lanemask_lt());
+                uint32_t old = 0;
+                if (valid[b]) old = whist[wave][dg[b]];
+                if (valid[b] && rank == 0) whist[wave][dg[b]] = old + (uint32_t)__popcll(peers);
+                loc[b] = old + rank;
             }
-            const uint32_t incl = msm::wave_incl_scan(s);
             __syncthreads();
-            if (lane == 63) tmp[wave] = incl;
-            __syncthreads();
-            uint32_t pre = 0;
-            for (int w = 0; w < wave; ++w) pre += tmp[w];
-            const uint32_t ex = pre + incl - s;
+            {
+                const int dgt = threadIdx.x;  // BK_THREADS == 256 digits
+                uint32_t s = 0;
 #pragma unroll
-            for (int w = 0; w < BK_WAVES; ++w) whist[w][dgt] += ex;
+                for (int w = 0; w < BK_WAVES; ++w) {
+                    const uint32_t v = whist[w][dgt];
+                    whist[w][dgt] = s;
+                    s += v;
+                }
+                const uint32_t incl = msm::wave_incl_scan(s);
+                __syncthreads();
+                if (lane == 63) tmp[wave] = incl;
+                __syncthreads();
+                uint32_t pre = 0;
+                for (int w = 0; w < wave; ++w) pre += tmp[w];
+                const uint32_t ex = pre + incl - s;
+#pragma unroll
+                for (int w = 0; w < BK_WAVES; ++w) whist[w][dgt] += ex;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int b = 0; b < BK_MAXB; ++b)
+                if (valid[b]) keysB[whist[wave][dg[b]] + loc[b]] = key[b];
+            __syncthreads();
+#pragma unroll
+            for (int b = 0; b < BK_MAXB; ++b) key[b] = valid[b] ? keysB[pos[b]] : ~0ull;
         }
-        __syncthreads();
+
+        // Runs of equal mix >> sort_lo.
+        const int rsh = 32 + p.sort_lo;
+        uint32_t head[BK_MAXB], nextHead[BK_MAXB];
+#pragma unroll
+        for (int b = 0; b < BK_MAXB; ++b) {
+            const uint32_t rk = (uint32_t)(key[b] >> rsh);
+            head[b] = valid[b] && (pos[b] == 0 || (uint32_t)(keysB[pos[b] - 1] >> rsh) != rk);
+            nextHead[b] = valid[b] && (pos[b] + 1 == m || (uint32_t)(keysB[pos[b] + 1] >> rsh) != rk);
+        }
+        uint32_t ex[BK_MAXB];
+        const uint32_t nruns = scan_wbl(head, ex, tmp);
 #pragma unroll
         for (int b = 0; b < BK_MAXB; ++b)
-            if (valid[b]) keysB[whist[wave][dg[b]] + loc[b]] = key[b];
+            if (head[b]) headPos[ex[b]] = (uint16_t)pos[b];
+        if (threadIdx.x == 0) headPos[nruns] = (uint16_t)m;
         __syncthreads();
-#pragma unroll
-        for (int b = 0; b < BK_MAXB; ++b) key[b] = valid[b] ? keysB[pos[b]] : ~0ull;
-    }
 
-    // Runs of equal mix >> sort_lo.
-    const int rsh = 32 + p.sort_lo;
-    uint32_t head[BK_MAXB], nextHead[BK_MAXB];
+        // Runs of length >= 2 with their pair counts.
+        uint32_t isLong[BK_MAXB], npair[BK_MAXB], len[BK_MAXB];
 #pragma unroll
-    for (int b = 0; b < BK_MAXB; ++b) {
-        const uint32_t rk = (uint32_t)(key[b] >> rsh);
-        head[b] = valid[b] && (pos[b] == 0 || (uint32_t)(keysB[pos[b] - 1] >> rsh) != rk);
-        nextHead[b] = valid[b] && (pos[b] + 1 == m || (uint32_t)(keysB[pos[b] + 1] >> rsh) != rk);
-    }
-    uint32_t ex[BK_MAXB];
-    const uint32_t nruns = scan_wbl(head, ex, tmp);
-#pragma unroll
-    for (int b = 0; b < BK_MAXB; ++b)
-        if (head[b]) headPos[ex[b]] = (uint16_t)pos[b];
-    if (threadIdx.x == 0) headPos[nruns] = (uint16_t)m;
-    __syncthreads();
-
-    // Runs of length >= 2 with their pair counts.
-    uint32_t isLong[BK_MAXB], npair[BK_MAXB], len[BK_MAXB];
-#pragma unroll
-    for (int b = 0; b < BK_MAXB; ++b) {
-        const int r = pos[b];
-        len[b] = r < (int)nruns ? (uint32_t)(headPos[r + 1] - headPos[r]) : 0u;
-        isLong[b] = len[b] >= 2;
-        npair[b] = isLong[b] ? len[b] * (len[b] - 1) / 2 : 0u;
-    }
-    uint32_t exL[BK_MAXB], exP[BK_MAXB];
-    const uint32_t nlong = scan_wbl(isLong, exL, tmp);
-    const uint32_t P = scan_wbl(npair, exP, tmp);
-#pragma unroll
-    for (int b = 0; b < BK_MAXB; ++b)
-        if (isLong[b]) {
-            runS[exL[b]] = headPos[pos[b]];
-            runL[exL[b]] = (uint16_t)len[b];
-            runP[exL[b]] = exP[b];
+        for (int b = 0; b < BK_MAXB; ++b) {
+            const int r = pos[b];
+            len[b] = r < (int)nruns ? (uint32_t)(headPos[r + 1] - headPos[r]) : 0u;
+            isLong[b] = len[b] >= 2;
+            npair[b] = isLong[b] ? len[b] * (len[b] - 1) / 2 : 0u;
         }
-    if (threadIdx.x == 0) runP[nlong] = P;
-    // Stage the strings of run members in sorted order.
+        uint32_t exL[BK_MAXB], exP[BK_MAXB];
+        const uint32_t nlong = scan_wbl(isLong, exL, tmp);
+        const uint32_t P = scan_wbl(npair, exP, tmp);
 #pragma unroll
-    for (int b = 0; b < BK_MAXB; ++b)
-        if (valid[b] && !(head[b] && nextHead[b])) {
-            const uint64_t idx = (uint32_t)key[b];
-#pragma unroll
-            for (int w = 0; w < W; ++w) sl[pos[b] * W + w] = p.S[idx * W + w];
-        }
-    __syncthreads();
-    if (P == 0) return;
-
-    // Flat loop over all pairs (a < b) inside runs, row-major per run; each
-    // lane takes BK_PAIR_CHUNK consecutive pairs.
-    for (uint32_t t0 = 0; t0 < P; t0 += BK_THREADS * BK_PAIR_CHUNK) {
-        const uint32_t t = t0 + threadIdx.x * BK_PAIR_CHUNK;
-        int r = 0, a = 0, bb = 1, L = 2, s0 = 0;
-        if (t < P) {
-            int lo = 0, hi2 = (int)nlong;
-            while (hi2 - lo > 1) {
-                const int mid = (lo + hi2) >> 1;
-                if (runP[mid] <= t) lo = mid;
-                else hi2 = mid;
+        for (int b = 0; b < BK_MAXB; ++b)
+            if (isLong[b]) {
+                runS[exL[b]] = headPos[pos[b]];
+                runL[exL[b]] = (uint16_t)len[b];
+                runP[exL[b]] = exP[b];
             }
-            r = lo;
-            L = runL[r];
-            s0 = runS[r];
-            const uint32_t u = t - runP[r];
-            // row a of the upper triangle starts at a (2L - a - 1) / 2
-            const float q = (float)(2 * L - 1);
-            int aa = (int)((q - sqrtf(q * q - 8.0f * (float)u)) * 0.5f);
-            aa = max(0, min(aa, L - 2));
-            while (aa < L - 2 && (uint32_t)((aa + 1) * (2 * L - aa - 2) / 2) <= u) ++aa;
-            while (aa > 0 && (uint32_t)(aa * (2 * L - aa - 1) / 2) > u) --aa;
-            a = aa;
-            bb = a + 1 + (int)(u - (uint32_t)(a * (2 * L - a - 1) / 2));
-        }
-        for (int q = 0; q < BK_PAIR_CHUNK; ++q) {
-            const bool live = t + q < P;
-            bool ok = false;
-            uint32_t i = 0, j = 0;
-            if (live) {
-                const int pa = s0 + a, pb = s0 + bb;
-                ok = pair_ok<W>(&sl[pa * W], &sl[pb * W], p, keep, hi, bmL);
-                i = (uint32_t)keysB[pa];
-                j = (uint32_t)keysB[pb];
-                if (++bb == L) {
-                    ++a;
-                    bb = a + 1;
-                    if (a >= L - 1) {
-                        ++r;
-                        a = 0;
-                        bb = 1;
-                        if (r < (int)nlong) {
-                            L = runL[r];
-                            s0 = runS[r];
+        if (threadIdx.x == 0) runP[nlong] = P;
+        // Stage the strings of run members in sorted order.
+#pragma unroll
+        for (int b = 0; b < BK_MAXB; ++b)
+            if (valid[b] && !(head[b] && nextHead[b])) {
+                const uint64_t idx = (uint32_t)key[b];
+#pragma unroll
+                for (int w = 0; w < W; ++w) sl[pos[b] * W + w] = p.S[idx * W + w];
+            }
+        __syncthreads();
+        if (P == 0) continue;
+
+        // Flat loop over all pairs (a < b) inside runs, row-major per run;
+        // each lane takes BK_PAIR_CHUNK consecutive pairs.
+        for (uint32_t t0 = 0; t0 < P; t0 += BK_THREADS * BK_PAIR_CHUNK) {
+            const uint32_t t = t0 + threadIdx.x * BK_PAIR_CHUNK;
+            int r = 0, a = 0, bb = 1, L = 2, s0 = 0;
+            if (t < P) {
+                int lo = 0, hi2 = (int)nlong;
+                while (hi2 - lo > 1) {
+                    const int mid = (lo + hi2) >> 1;
+                    if (runP[mid] <= t) lo = mid;
+                    else hi2 = mid;
+                }
+                r = lo;
+                L = runL[r];
+                s0 = runS[r];
+                const uint32_t u = t - runP[r];
+                // row a of the upper triangle starts at a (2L - a - 1) / 2
+                const float q = (float)(2 * L - 1);
+                int aa = (int)((q - sqrtf(q * q - 8.0f * (float)u)) * 0.5f);
+                aa = max(0, min(aa, L - 2));
+                while (aa < L - 2 && (uint32_t)((aa + 1) * (2 * L - aa - 2) / 2) <= u) ++aa;
+                while (aa > 0 && (uint32_t)(aa * (2 * L - aa - 1) / 2) > u) --aa;
+                a = aa;
+                bb = a + 1 + (int)(u - (uint32_t)(a * (2 * L - a - 1) / 2));
+            }
+            for (int q = 0; q < BK_PAIR_CHUNK; ++q) {
+                const bool live = t + q < P;
+                bool ok = false;
+                uint32_t i = 0, j = 0;
+                if (live) {
+                    const int pa = s0 + a, pb = s0 + bb;
+                    ok = pair_ok<W>(&sl[pa * W], &sl[pb * W], p, keep, hi, bmL);
+                    i = (uint32_t)keysB[pa];
+                    j = (uint32_t)keysB[pb];
+                    if (++bb == L) {
+                        ++a;
+                        bb = a + 1;
+                        if (a >= L - 1) {
+                            ++r;
+                            a = 0;
+                            bb = 1;
+                            if (r < (int)nlong) {
+                                L = runL[r];
+                                s0 = runS[r];
+                            }
                         }
                     }
                 }
+                out.push(ok, i < j ? i : j, i < j ? j : i);
             }
-            const unsigned long long slot = msm::wave_append(ok, p.counter);
-            write_pair(p, ok, slot, i, j);
         }
+        out.maybe_flush(BK_OUT / 2);
     }
+    out.flush();
 }
 
 // -------------------------------------------------------------------------
@@ -501,6 +504,11 @@ __global__ __launch_bounds__(BIG_TILE) void k_big(Params p, const Ovf* __restric
     __shared__ uint64_t kR[BIG_TILE], kC[BIG_TILE];
     __shared__ uint64_t sR[BIG_TILE * W], sC[BIG_TILE * W];
     __shared__ uint64_t bmL[MAXK * W];
+    __shared__ uint2 obuf[BK_OUT];
+    __shared__ uint32_t ocnt;
+    __shared__ unsigned long long ogb;
+    if (threadIdx.x == 0) ocnt = 0;
+    msm::PairStager<BK_OUT> out{obuf, &ocnt, &ogb, p.pairs, p.cap, p.counter};
     const uint64_t tix = blockIdx.x;
     int lo = 0, hi2 = novf;
     while (hi2 - lo > 1) {
@@ -540,13 +548,16 @@ __global__ __launch_bounds__(BIG_TILE) void k_big(Params p, const Ovf* __restric
     const int ncol = (int)min<int64_t>(BIG_TILE, (int64_t)e.m - tb * BIG_TILE);
     const uint32_t mine = (uint32_t)(kR[threadIdx.x] >> 32);
     const bool diag = ta == tb;
+    const uint32_t ii = (uint32_t)kR[threadIdx.x];
     for (int jj = 0; jj < ncol; ++jj) {
         const uint64_t kc = kC[jj];
         bool ok = rv && (!diag || jj > (int)threadIdx.x) && (uint32_t)(kc >> 32) == mine;
         if (ok) ok = pair_ok<W>(&sR[threadIdx.x * W], &sC[jj * W], p, keep, hi, bmL);
-        const unsigned long long slot = msm::wave_append(ok, p.counter);
-        write_pair(p, ok, slot, (uint32_t)kR[threadIdx.x], (uint32_t)kc);
+        const uint32_t jv = (uint32_t)kc;
+        out.push(ok, ii < jv ? ii : jv, ii < jv ? jv : ii);
+        if ((jj & 7) == 7) out.maybe_flush(BK_OUT / 2);
     }
+    out.flush();
 }
 
 __global__ void k_zero_u64(unsigned long long* a, int n)
@@ -706,7 +717,8 @@ msm_status run_enumerate(msm_ctx* ctx, const uint64_t* S, int64_t n, int ell, in
         }
         {
             msm::KernelTimer kt(ctx, stream, "k_bucket");
-            hipLaunchKernelGGL((k_bucket<W>), dim3(nb, cc), dim3(BK_THREADS), 0, stream, p);
+            hipLaunchKernelGGL((k_bucket<W>), dim3((nb + BK_GROUP - 1) / BK_GROUP, cc), dim3(BK_THREADS), 0, stream,
+                               p);
         }
         MSM_HIP(ctx, hipGetLastError());
         MSM_HIP(ctx, hipMemcpyAsync(ctx->host_words, d_ovfc, sizeof(uint32_t), hipMemcpyDeviceToHost, stream));

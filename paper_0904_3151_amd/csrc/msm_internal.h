@@ -127,4 +127,58 @@ __device__ __forceinline__ unsigned long long wave_append(bool ok, unsigned long
     return base + (unsigned long long)__popcll(mask & lanemask_lt());
 }
 
+// Collects a workgroup's output pairs in LDS so that the global output
+// counter is touched once per flush instead of once per wave step.
+// `buf` (CAPB entries) and `cnt` live in LDS; `cnt` must start at 0.
+// push() is called by every lane of a wave (converged); pairs that do not
+// fit in LDS are appended to the global list directly. flush() and
+// maybe_flush() are called by every thread of the workgroup.
+template <int CAPB>
+struct PairStager {
+    uint2* buf;
+    uint32_t* cnt;
+    unsigned long long* gbase;  // LDS scratch word for the flush
+    uint32_t* out;
+    unsigned long long cap;
+    unsigned long long* counter;
+
+    __device__ __forceinline__ void push(bool ok, uint32_t i, uint32_t j)
+    {
+        const uint64_t mask = __ballot(ok);
+        if (!mask) return;
+        const int leader = __builtin_ctzll(mask);
+        uint32_t base = 0;
+        if (__lane_id() == leader) base = atomicAdd(cnt, (uint32_t)__popcll(mask));
+        base = __shfl(base, leader, 64);
+        const uint32_t pos = base + (uint32_t)__popcll(mask & lanemask_lt());
+        const bool spill = ok && pos >= (uint32_t)CAPB;
+        if (ok && !spill) buf[pos] = make_uint2(i, j);
+        const unsigned long long slot = wave_append(spill, counter);
+        if (spill && slot < cap) *reinterpret_cast<uint2*>(out + 2 * slot) = make_uint2(i, j);
+    }
+
+    __device__ __forceinline__ void flush()
+    {
+        __syncthreads();
+        const uint32_t n = min(*cnt, (uint32_t)CAPB);
+        if (n > 0) {
+            if (threadIdx.x == 0) *gbase = atomicAdd(counter, (unsigned long long)n);
+            __syncthreads();
+            const unsigned long long g = *gbase;
+            for (uint32_t e = threadIdx.x; e < n; e += blockDim.x)
+                if (g + e < cap) *reinterpret_cast<uint2*>(out + 2 * (g + e)) = buf[e];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) *cnt = 0;
+        __syncthreads();
+    }
+
+    // Flushes when at least `threshold` pairs are staged.
+    __device__ __forceinline__ void maybe_flush(uint32_t threshold)
+    {
+        __syncthreads();
+        if (*cnt >= threshold) flush();
+    }
+};
+
 }  // namespace msm

@@ -12,6 +12,7 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 constexpr int VF_THREADS = 256;
 constexpr int VF_TEAM = 16;
+constexpr int VF_OUT = 1024;  // staged kept pairs per workgroup
 
 template <int METRIC, bool VEC4>
 __global__ __launch_bounds__(VF_THREADS) void k_verify(const float* __restrict__ X, int64_t n, int d,
@@ -20,6 +21,12 @@ __global__ __launch_bounds__(VF_THREADS) void k_verify(const float* __restrict__
                                                        unsigned long long cap, unsigned long long* counter,
                                                        uint32_t* bad)
 {
+    __shared__ uint2 obuf[VF_OUT];
+    __shared__ uint32_t ocnt;
+    __shared__ unsigned long long ogb;
+    if (threadIdx.x == 0) ocnt = 0;
+    __syncthreads();
+    msm::PairStager<VF_OUT> stage{obuf, &ocnt, &ogb, out, cap, counter};
     const int tl = threadIdx.x & (VF_TEAM - 1);
     const int64_t team = ((int64_t)blockIdx.x * VF_THREADS + threadIdx.x) / VF_TEAM;
     const int64_t nteams = ((int64_t)gridDim.x * VF_THREADS) / VF_TEAM;
@@ -89,9 +96,10 @@ __global__ __launch_bounds__(VF_THREADS) void k_verify(const float* __restrict__
                 keep = dist <= eps;
             }
         }
-        const unsigned long long slot = msm::wave_append(keep, counter);
-        if (keep && slot < cap) *reinterpret_cast<uint2*>(out + 2 * slot) = make_uint2(i, j);
+        stage.push(keep, i, j);
+        if ((it & 15) == 15) stage.maybe_flush(VF_OUT / 2);
     }
+    stage.flush();
 }
 
 __global__ void k_zero_words(unsigned long long* a, int n)
