@@ -10,11 +10,12 @@
 //                 LDS histograms per tile (k_part_count), a column scan of
 //                 the (tile, bucket) counts (k_part_scan), and a scatter of
 //                 (mix << 32 | index) into bucket order (k_part_scatter).
-//   2. bucket     one workgroup per bucket (about 512 points): a stable LSD
-//                 radix sort in LDS on the next 16 bits of the mix (two 8-bit
-//                 digits, ranked with wave64 ballots and a wave prefix scan),
-//                 segmentation into runs of equal mix, and a flat, balanced
-//                 loop over all pairs inside runs (k_bucket).
+//   2. bucket     a workgroup takes a few buckets (about 512 points each):
+//                 the next 11 bits of the mix are counted in an LDS
+//                 histogram (the second radix digit), whose bins with two or
+//                 more members are the runs; a wavefront prefix scan places
+//                 the run members in LDS and a flat, balanced loop tests all
+//                 pairs inside runs (k_bucket).
 //   3. overflow   buckets larger than the LDS capacity are tested tile by
 //                 tile straight from HBM (k_big).
 //
@@ -48,17 +49,24 @@ constexpr int BK_MAXB = 4;                        // 64-element batches per wave
 constexpr int BK_CAP = BK_WAVES * 64 * BK_MAXB;   // largest bucket sorted in LDS
 constexpr int BK_PAIR_CHUNK = 8;                  // consecutive pairs per lane
 constexpr int BK_GROUP = 8;                       // buckets per workgroup
-constexpr int BK_OUT = 2048;                      // staged output pairs per workgroup
+constexpr int BK_OUT = 512;                       // staged output pairs per workgroup
+constexpr int BK_DIGIT = 10;                      // mix bits counted inside a bucket
+constexpr int BK_BINS = 1 << BK_DIGIT;
 constexpr int BIG_TILE = 256;
 constexpr int MAX_BUCKETS = 8192;
 constexpr int TARGET_BUCKET = 512;
 
-struct Combo {             // one set B of masked blocks
-    uint64_t keep[MAXW];   // characters below ell outside the blocks of B
-    uint64_t hi;           // blocks of B above the smallest block not in B
-    uint64_t pad[3];
+constexpr int MAXHI = 4;   // blocks of `hi` tested from unrolled masks
+
+struct Combo {                    // one set B of masked blocks
+    uint64_t keep[MAXW];          // characters below ell outside the blocks of B
+    uint64_t hi;                  // blocks of B above the smallest block not in B
+    int32_t nhi;                  // number of blocks in hi
+    int32_t pad0;
+    uint64_t pad1[2];
+    uint64_t himask[MAXHI][MAXW]; // character masks of the first MAXHI blocks of hi
 };
-static_assert(sizeof(Combo) == 64, "Combo layout");
+static_assert(sizeof(Combo) == 192, "Combo layout");
 
 struct Ovf {
     uint32_t c, beg, m, pad;
@@ -75,6 +83,7 @@ struct Params {
     int nb;                  // 1 << r1
     int sort_lo;             // runs share mix >> sort_lo
     int T, nt;               // partition tile size and count
+    int units;               // combinations of the group x tiles
     uint32_t* counts;        // [c][t][b] tile counts, then tile offsets
     uint32_t* base;          // [c][nb + 1] bucket starts
     uint64_t* part;          // [c][n] (mix << 32 | index) in bucket order
@@ -118,13 +127,30 @@ __device__ __forceinline__ void load_keep(const Combo* cb, uint64_t (&keep)[W])
 
 // -------------------------------------------------------------------------
 // 1. partition
+//
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own
+// L2. The (combination, tile) units are cut into 8 contiguous ranges in
+// combination-major order and XCD x runs range x, so all tiles of a
+// combination scatter through one L2, where the partial lines that
+// neighbouring tiles write into the same bucket can merge.
+constexpr int NUM_XCD = 8;
+
+__device__ __forceinline__ bool xcd_unit(int units, int& cl, int& t, int nt)
+{
+    const int per = (units + NUM_XCD - 1) / NUM_XCD;
+    const int u = (int)(blockIdx.x % NUM_XCD) * per + (int)(blockIdx.x / NUM_XCD);
+    if (u >= units) return false;
+    cl = u / nt;
+    t = u % nt;
+    return true;
+}
 
 template <int W>
 __global__ __launch_bounds__(PART_THREADS) void k_part_count(Params p)
 {
     extern __shared__ uint32_t hist[];
-    const int cl = blockIdx.x;
-    const int t = blockIdx.y;
+    int cl, t;
+    if (!xcd_unit(p.units, cl, t, p.nt)) return;
     uint64_t keep[W];
     load_keep<W>(p.combos + cl, keep);
     for (int b = threadIdx.x; b < p.nb; b += PART_THREADS) hist[b] = 0;
@@ -197,8 +223,8 @@ template <int W>
 __global__ __launch_bounds__(PART_THREADS) void k_part_scatter(Params p)
 {
     extern __shared__ uint32_t cursor[];
-    const int cl = blockIdx.x;
-    const int t = blockIdx.y;
+    int cl, t;
+    if (!xcd_unit(p.units, cl, t, p.nt)) return;
     uint64_t keep[W];
     load_keep<W>(p.combos + cl, keep);
     const uint32_t* off = p.counts + ((size_t)cl * p.nt + t) * p.nb;
@@ -248,71 +274,126 @@ __device__ __forceinline__ bool pair_ok(const uint64_t* a, const uint64_t* b, co
     return ok;
 }
 
-// Exclusive prefix over values laid out as position = wave*256 + b*64 + lane
-// (the element layout of k_bucket). Returns the block total.
-__device__ __forceinline__ uint32_t scan_wbl(const uint32_t (&v)[BK_MAXB], uint32_t (&ex)[BK_MAXB],
-                                             uint32_t* tmp)
+// The same test with the masks of `hi` read from the combination (scalar
+// registers) when it has at most MAXHI blocks.
+template <int W>
+__device__ __forceinline__ bool pair_ok_fast(const uint64_t* a, const uint64_t* b, const Params& p,
+                                             const uint64_t (&keep)[W], const Combo* cb, uint64_t hi, int nhi,
+                                             const uint64_t* __restrict__ bmL)
 {
-    const int wave = threadIdx.x >> 6;
-    uint32_t carry = 0;
+    uint64_t x[W];
+    int ham = 0;
+    uint64_t outside = 0;
 #pragma unroll
-    for (int b = 0; b < BK_MAXB; ++b) {
-        const uint32_t incl = msm::wave_incl_scan(v[b]);
-        ex[b] = carry + incl - v[b];
-        carry += __shfl(incl, 63, 64);
+    for (int w = 0; w < W; ++w) {
+        x[w] = (a[w] ^ b[w]) & p.valid[w];
+        ham += __popcll(x[w]);
+        outside |= x[w] & keep[w];
     }
-    __syncthreads();
-    if ((threadIdx.x & 63) == 0) tmp[wave] = carry;
-    __syncthreads();
-    uint32_t pre = 0, total = 0;
+    bool ok = (ham <= p.h) & (outside == 0);
+    if (nhi <= MAXHI) {
 #pragma unroll
-    for (int w = 0; w < BK_WAVES; ++w) {
-        const uint32_t t = tmp[w];
-        if (w < wave) pre += t;
-        total += t;
+        for (int s = 0; s < MAXHI; ++s) {
+            if (s < nhi) {
+                uint64_t any = 0;
+#pragma unroll
+                for (int w = 0; w < W; ++w) any |= x[w] & cb->himask[s][w];
+                ok &= any != 0;
+            }
+        }
+        return ok;
     }
+    uint64_t need = hi;
+    while (need) {
+        const int blk = __builtin_ctzll(need);
+        need &= need - 1;
+        uint64_t any = 0;
 #pragma unroll
-    for (int b = 0; b < BK_MAXB; ++b) ex[b] += pre;
-    return total;
+        for (int w = 0; w < W; ++w) any |= x[w] & bmL[blk * W + w];
+        ok &= any != 0;
+    }
+    return ok;
 }
 
 // -------------------------------------------------------------------------
 // 2. buckets, BK_GROUP consecutive ones per workgroup
+//
+// Inside a bucket one more radix digit (BK_DIGIT bits of the mix, below the
+// bucket bits) is counted in an LDS histogram; the count returned by each
+// element's atomic is its rank in its bin. The histogram is the run
+// segmentation: a bin with c >= 2 members is a run (equal masked strings
+// always share a bin) with c (c - 1) / 2 candidate pairs; singleton bins are
+// dropped. The first member of each run claims the run's index and its place
+// in a compact LDS array of run members with one packed 64-bit LDS atomic,
+// so no scan over the bins is needed. Members are scattered there with their
+// strings; each run then either claims a range of the flat pair index space
+// the same way or is dropped when it cannot hold a pair to write (below),
+// and a flat loop over the claimed pairs tests them. Bins that mix several
+// masked strings only add candidates, which the exact test rejects.
 
 template <int W>
 __global__ __launch_bounds__(BK_THREADS) void k_bucket(Params p)
 {
+    __shared__ uint32_t hist[BK_BINS];
+    __shared__ uint16_t binStart[BK_BINS];
+    __shared__ uint16_t binRun[BK_BINS];
     __shared__ uint64_t keysB[BK_CAP];
     __shared__ uint64_t sl[BK_CAP * W];
-    __shared__ uint32_t whist[BK_WAVES][256];
-    __shared__ uint16_t headPos[BK_CAP + 1];
-    __shared__ uint16_t runS[BK_CAP];
-    __shared__ uint16_t runL[BK_CAP];
-    __shared__ uint32_t runP[BK_CAP + 1];
+    __shared__ uint16_t runS[BK_CAP / 2];
+    __shared__ uint16_t runL[BK_CAP / 2];
+    __shared__ unsigned long long runVar[BK_CAP / 2 * W];  // bits that vary inside the run
+    __shared__ uint16_t liveS[BK_CAP / 2];
+    __shared__ uint16_t liveL[BK_CAP / 2];
+    __shared__ uint32_t liveP[BK_CAP / 2];
     __shared__ uint64_t bmL[MAXK * W];
-    __shared__ uint32_t tmp[BK_WAVES];
+    __shared__ unsigned long long claimRun;   // runs << 32 | members
+    __shared__ unsigned long long claimPair;  // live runs << 32 | pairs
     __shared__ uint2 obuf[BK_OUT];
     __shared__ uint32_t ocnt;
     __shared__ unsigned long long ogb;
 
     const int cl = blockIdx.y;
-    const int wave = threadIdx.x >> 6;
-    const int lane = threadIdx.x & 63;
     const Combo* cb = p.combos + cl;
     uint64_t keep[W];
     load_keep<W>(cb, keep);
     const uint64_t hi = cb->hi;
+    const int nhi = cb->nhi;
     for (int e = threadIdx.x; e < p.k * W; e += BK_THREADS) bmL[e] = p.bm[(e / W) * MAXW + (e % W)];
+    for (int e = threadIdx.x; e < BK_BINS; e += BK_THREADS) hist[e] = 0;
     if (threadIdx.x == 0) ocnt = 0;
     msm::PairStager<BK_OUT> out{obuf, &ocnt, &ogb, p.pairs, p.cap, p.counter};
     const uint32_t* base = p.base + (size_t)cl * (p.nb + 1);
+    const uint64_t* part = p.part + (size_t)cl * p.n;
     const int bk0 = blockIdx.x * BK_GROUP;
     const int bk1 = min(p.nb, bk0 + BK_GROUP);
+    const int dsh = 32 + p.sort_lo;
+
+    // keys of the current bucket, loaded one bucket ahead
+    uint64_t key[BK_MAXB];
+    uint32_t nbeg = base[bk0];
+    uint32_t ncnt = base[bk0 + 1] - nbeg;
+#pragma unroll
+    for (int b = 0; b < BK_MAXB; ++b) {
+        const int pos = threadIdx.x + b * BK_THREADS;
+        key[b] = (ncnt <= (uint32_t)BK_CAP && pos < (int)ncnt) ? part[nbeg + pos] : ~0ull;
+    }
 
     for (int bk = bk0; bk < bk1; ++bk) {
-        __syncthreads();  // the previous bucket's LDS data is no longer read
-        const uint32_t beg = base[bk];
-        const uint32_t cnt = base[bk + 1] - beg;
+        const uint32_t beg = nbeg;
+        const uint32_t cnt = ncnt;
+        uint64_t cur[BK_MAXB];
+#pragma unroll
+        for (int b = 0; b < BK_MAXB; ++b) cur[b] = key[b];
+        if (bk + 1 < bk1) {
+            nbeg = base[bk + 1];
+            ncnt = base[bk + 2] - nbeg;
+#pragma unroll
+            for (int b = 0; b < BK_MAXB; ++b) {
+                const int pos = threadIdx.x + b * BK_THREADS;
+                key[b] = (ncnt <= (uint32_t)BK_CAP && pos < (int)ncnt) ? part[nbeg + pos] : ~0ull;
+            }
+        }
+        __syncthreads();  // LDS of the previous bucket is free, hist is zero
         if (cnt < 2) continue;
         if (cnt > (uint32_t)BK_CAP) {
             if (threadIdx.x == 0) {
@@ -322,137 +403,121 @@ __global__ __launch_bounds__(BK_THREADS) void k_bucket(Params p)
             continue;
         }
         const int m = (int)cnt;
-        const uint64_t* part = p.part + (size_t)cl * p.n + beg;
-        uint64_t key[BK_MAXB];
-        int pos[BK_MAXB];
-        bool valid[BK_MAXB];
-#pragma unroll
-        for (int b = 0; b < BK_MAXB; ++b) {
-            pos[b] = wave * (64 * BK_MAXB) + b * 64 + lane;
-            valid[b] = pos[b] < m;
-            key[b] = valid[b] ? part[pos[b]] : ~0ull;
+        if (threadIdx.x == 0) {
+            claimRun = 0;
+            claimPair = 0;
         }
 
-        // Stable LSD radix sort on mix bits [sort_lo, sort_lo + 16): two
-        // 8-bit digits. Lanes with equal digits in a batch of 64 find each
-        // other with eight ballots; ranks follow position order, so each
-        // pass is stable.
-#pragma unroll
-        for (int pass = 0; pass < 2; ++pass) {
-            const int sh = 32 + p.sort_lo + 8 * pass;
-            for (int i = lane; i < 256; i += 64) whist[wave][i] = 0;
-            __syncthreads();
-            uint32_t loc[BK_MAXB];
-            uint32_t dg[BK_MAXB];
-#pragma unroll
-            for (int b = 0; b < BK_MAXB; ++b) {
-                dg[b] = (uint32_t)(key[b] >> sh) & 0xFFu;
-                uint64_t peers = __ballot(valid[b]);
-#pragma unroll
-                for (int bit = 0; bit < 8; ++bit) {
-                    const bool set = (dg[b] >> bit) & 1u;
-                    const uint64_t bb = __ballot(set);
-                    peers &= set ? bb : ~bb;
-                }
-                const uint32_t rank = (uint32_t)__popcll(peers & msm::lanemask_lt());
-                uint32_t old = 0;
-                if (valid[b]) old = whist[wave][dg[b]];
-                if (valid[b] && rank == 0) whist[wave][dg[b]] = old + (uint32_t)__popcll(peers);
-                loc[b] = old + rank;
-            }
-            __syncthreads();
-            {
-                const int dgt = threadIdx.x;  // BK_THREADS == 256 digits
-                uint32_t s = 0;
-#pragma unroll
-                for (int w = 0; w < BK_WAVES; ++w) {
-                    const uint32_t v = whist[w][dgt];
-                    whist[w][dgt] = s;
-                    s += v;
-                }
-                const uint32_t incl = msm::wave_incl_scan(s);
-                __syncthreads();
-                if (lane == 63) tmp[wave] = incl;
-                __syncthreads();
-                uint32_t pre = 0;
-                for (int w = 0; w < wave; ++w) pre += tmp[w];
-                const uint32_t ex = pre + incl - s;
-#pragma unroll
-                for (int w = 0; w < BK_WAVES; ++w) whist[w][dgt] += ex;
-            }
-            __syncthreads();
-#pragma unroll
-            for (int b = 0; b < BK_MAXB; ++b)
-                if (valid[b]) keysB[whist[wave][dg[b]] + loc[b]] = key[b];
-            __syncthreads();
-#pragma unroll
-            for (int b = 0; b < BK_MAXB; ++b) key[b] = valid[b] ? keysB[pos[b]] : ~0ull;
-        }
-
-        // Runs of equal mix >> sort_lo.
-        const int rsh = 32 + p.sort_lo;
-        uint32_t head[BK_MAXB], nextHead[BK_MAXB];
+        // histogram of the in-bucket digit; the returned count is the rank
+        uint32_t dig[BK_MAXB], rank[BK_MAXB];
 #pragma unroll
         for (int b = 0; b < BK_MAXB; ++b) {
-            const uint32_t rk = (uint32_t)(key[b] >> rsh);
-            head[b] = valid[b] && (pos[b] == 0 || (uint32_t)(keysB[pos[b] - 1] >> rsh) != rk);
-            nextHead[b] = valid[b] && (pos[b] + 1 == m || (uint32_t)(keysB[pos[b] + 1] >> rsh) != rk);
+            const int pos = threadIdx.x + b * BK_THREADS;
+            dig[b] = (uint32_t)(cur[b] >> dsh) & (BK_BINS - 1);
+            rank[b] = pos < m ? atomicAdd(&hist[dig[b]], 1u) : 0xFFFFFFFFu;
         }
-        uint32_t ex[BK_MAXB];
-        const uint32_t nruns = scan_wbl(head, ex, tmp);
-#pragma unroll
-        for (int b = 0; b < BK_MAXB; ++b)
-            if (head[b]) headPos[ex[b]] = (uint16_t)pos[b];
-        if (threadIdx.x == 0) headPos[nruns] = (uint16_t)m;
         __syncthreads();
 
-        // Runs of length >= 2 with their pair counts.
-        uint32_t isLong[BK_MAXB], npair[BK_MAXB], len[BK_MAXB];
+        // the first member of each run claims the run and its member range
+        uint32_t c[BK_MAXB];
 #pragma unroll
         for (int b = 0; b < BK_MAXB; ++b) {
-            const int r = pos[b];
-            len[b] = r < (int)nruns ? (uint32_t)(headPos[r + 1] - headPos[r]) : 0u;
-            isLong[b] = len[b] >= 2;
-            npair[b] = isLong[b] ? len[b] * (len[b] - 1) / 2 : 0u;
+            c[b] = rank[b] != 0xFFFFFFFFu ? hist[dig[b]] : 0u;
+            if (rank[b] == 0 && c[b] >= 2) {
+                const unsigned long long old = atomicAdd(&claimRun, (1ull << 32) | (unsigned long long)c[b]);
+                const uint32_t r = (uint32_t)(old >> 32);
+                const uint32_t ms = (uint32_t)old;
+                binStart[dig[b]] = (uint16_t)ms;
+                binRun[dig[b]] = (uint16_t)r;
+                runS[r] = (uint16_t)ms;
+                runL[r] = (uint16_t)c[b];
+#pragma unroll
+                for (int w = 0; w < W; ++w) runVar[r * W + w] = 0ull;
+            }
         }
-        uint32_t exL[BK_MAXB], exP[BK_MAXB];
-        const uint32_t nlong = scan_wbl(isLong, exL, tmp);
-        const uint32_t P = scan_wbl(npair, exP, tmp);
-#pragma unroll
-        for (int b = 0; b < BK_MAXB; ++b)
-            if (isLong[b]) {
-                runS[exL[b]] = headPos[pos[b]];
-                runL[exL[b]] = (uint16_t)len[b];
-                runP[exL[b]] = exP[b];
-            }
-        if (threadIdx.x == 0) runP[nlong] = P;
-        // Stage the strings of run members in sorted order.
-#pragma unroll
-        for (int b = 0; b < BK_MAXB; ++b)
-            if (valid[b] && !(head[b] && nextHead[b])) {
-                const uint64_t idx = (uint32_t)key[b];
-#pragma unroll
-                for (int w = 0; w < W; ++w) sl[pos[b] * W + w] = p.S[idx * W + w];
-            }
         __syncthreads();
+
+        // scatter run members and gather their strings
+#pragma unroll
+        for (int b = 0; b < BK_MAXB; ++b) {
+            if (c[b] >= 2) {
+                const uint32_t q = binStart[dig[b]] + rank[b];
+                keysB[q] = cur[b];
+                const uint64_t idx = (uint32_t)cur[b];
+#pragma unroll
+                for (int w = 0; w < W; ++w) sl[q * W + w] = p.S[idx * W + w];
+            }
+        }
+        const uint32_t nruns = (uint32_t)(claimRun >> 32);
+        __syncthreads();
+        // Each member ORs its difference from the run's first member into
+        // the run's mask of varying bits; the histogram is cleared for the
+        // next bucket.
+#pragma unroll
+        for (int b = 0; b < BK_MAXB; ++b) {
+            if (rank[b] != 0xFFFFFFFFu) {
+                if (hi && c[b] >= 2 && rank[b] > 0) {
+                    const uint32_t first = binStart[dig[b]];
+                    const uint32_t q = first + rank[b];
+                    const uint32_t r = binRun[dig[b]];
+#pragma unroll
+                    for (int w = 0; w < W; ++w) {
+                        const uint64_t x = sl[q * W + w] ^ sl[first * W + w];
+                        if (x) atomicOr(&runVar[r * W + w], (unsigned long long)x);
+                    }
+                }
+                hist[dig[b]] = 0;
+            }
+        }
+        if (nruns == 0) continue;
+        if (hi) __syncthreads();
+
+        // Each run claims its pairs, unless it cannot hold a pair to write:
+        // a pair is written only if it differs in every block of `hi`, so a
+        // block of `hi` that is constant over the whole run rules it out.
+        for (uint32_t r = threadIdx.x; r < nruns; r += BK_THREADS) {
+            const int s0 = runS[r], L = runL[r];
+            bool live = true;
+            uint64_t need = hi;
+            while (live && need) {
+                const int blk = __builtin_ctzll(need);
+                need &= need - 1;
+                uint64_t any = 0;
+#pragma unroll
+                for (int w = 0; w < W; ++w) any |= runVar[r * W + w] & p.valid[w] & bmL[blk * W + w];
+                live = any != 0;
+            }
+            if (live) {
+                const unsigned long long old =
+                    atomicAdd(&claimPair, (1ull << 32) | (unsigned long long)(L * (L - 1) / 2));
+                const uint32_t q = (uint32_t)(old >> 32);
+                liveS[q] = (uint16_t)s0;
+                liveL[q] = (uint16_t)L;
+                liveP[q] = (uint32_t)old;
+            }
+        }
+        __syncthreads();
+        const uint32_t nlive = (uint32_t)(claimPair >> 32);
+        const uint32_t P = (uint32_t)claimPair;
         if (P == 0) continue;
 
-        // Flat loop over all pairs (a < b) inside runs, row-major per run;
-        // each lane takes BK_PAIR_CHUNK consecutive pairs.
+        // Flat loop over all claimed pairs (a < b), row-major per run; each
+        // lane tests BK_PAIR_CHUNK consecutive pairs, keeps the results in a
+        // bit mask and appends the passing ones once per chunk.
         for (uint32_t t0 = 0; t0 < P; t0 += BK_THREADS * BK_PAIR_CHUNK) {
             const uint32_t t = t0 + threadIdx.x * BK_PAIR_CHUNK;
             int r = 0, a = 0, bb = 1, L = 2, s0 = 0;
             if (t < P) {
-                int lo = 0, hi2 = (int)nlong;
+                int lo = 0, hi2 = (int)nlive;
                 while (hi2 - lo > 1) {
                     const int mid = (lo + hi2) >> 1;
-                    if (runP[mid] <= t) lo = mid;
+                    if (liveP[mid] <= t) lo = mid;
                     else hi2 = mid;
                 }
                 r = lo;
-                L = runL[r];
-                s0 = runS[r];
-                const uint32_t u = t - runP[r];
+                L = liveL[r];
+                s0 = liveS[r];
+                const uint32_t u = t - liveP[r];
                 // row a of the upper triangle starts at a (2L - a - 1) / 2
                 const float q = (float)(2 * L - 1);
                 int aa = (int)((q - sqrtf(q * q - 8.0f * (float)u)) * 0.5f);
@@ -462,31 +527,66 @@ __global__ __launch_bounds__(BK_THREADS) void k_bucket(Params p)
                 a = aa;
                 bb = a + 1 + (int)(u - (uint32_t)(a * (2 * L - a - 1) / 2));
             }
+            uint32_t okbits = 0;
+            uint32_t pi[BK_PAIR_CHUNK], pj[BK_PAIR_CHUNK];
+#pragma unroll
             for (int q = 0; q < BK_PAIR_CHUNK; ++q) {
                 const bool live = t + q < P;
-                bool ok = false;
-                uint32_t i = 0, j = 0;
-                if (live) {
-                    const int pa = s0 + a, pb = s0 + bb;
-                    ok = pair_ok<W>(&sl[pa * W], &sl[pb * W], p, keep, hi, bmL);
-                    i = (uint32_t)keysB[pa];
-                    j = (uint32_t)keysB[pb];
-                    if (++bb == L) {
-                        ++a;
-                        bb = a + 1;
-                        if (a >= L - 1) {
-                            ++r;
-                            a = 0;
-                            bb = 1;
-                            if (r < (int)nlong) {
-                                L = runL[r];
-                                s0 = runS[r];
-                            }
-                        }
+                const int pa = min(s0 + a, BK_CAP - 1), pb = min(s0 + bb, BK_CAP - 1);
+                const uint64_t ka = keysB[pa], kb = keysB[pb];
+                pi[q] = (uint32_t)ka;
+                pj[q] = (uint32_t)kb;
+                const bool ok = live && (ka >> 32) == (kb >> 32) &&
+                                pair_ok_fast<W>(&sl[pa * W], &sl[pb * W], p, keep, cb, hi, nhi, bmL);
+                okbits |= (uint32_t)ok << q;
+                if (++bb == L) {
+                    ++a;
+                    bb = a + 1;
+                    if (a >= L - 1) {
+                        ++r;
+                        a = 0;
+                        bb = 1;
+                        const int rr = min(r, (int)nlive - 1);
+                        L = liveL[rr];
+                        s0 = liveS[rr];
                     }
                 }
-                out.push(ok, i < j ? i : j, i < j ? j : i);
             }
+            // one append per lane per chunk: wave prefix of the counts, one
+            // LDS atomic per wave
+            const uint32_t nmine = (uint32_t)__popc(okbits);
+            const uint32_t incl = msm::wave_incl_scan(nmine);
+            const uint32_t wtot = __shfl(incl, 63, 64);
+            uint32_t wbase = 0;
+            if (wtot) {
+                if (__lane_id() == 0) wbase = atomicAdd(&ocnt, wtot);
+                wbase = __shfl(wbase, 0, 64);
+            }
+            uint32_t slot = wbase + incl - nmine;
+            // slots at or above BK_OUT do not fit in LDS: they go to the
+            // global list directly, reserved with one atomic per wave
+            const uint32_t first_out = max(wbase, (uint32_t)BK_OUT);
+            const uint32_t nover = (wtot && wbase + wtot > (uint32_t)BK_OUT) ? wbase + wtot - first_out : 0u;
+            unsigned long long gbase = 0;
+            if (nover) {
+                if (__lane_id() == 0) gbase = atomicAdd(p.counter, (unsigned long long)nover);
+                gbase = __shfl(gbase, 0, 64);
+            }
+#pragma unroll
+            for (int q = 0; q < BK_PAIR_CHUNK; ++q) {
+                if ((okbits >> q) & 1u) {
+                    const uint32_t lo2 = pi[q] < pj[q] ? pi[q] : pj[q];
+                    const uint32_t hi3 = pi[q] < pj[q] ? pj[q] : pi[q];
+                    if (slot < (uint32_t)BK_OUT) {
+                        obuf[slot] = make_uint2(lo2, hi3);
+                    } else {
+                        const unsigned long long g = gbase + (slot - first_out);
+                        if (g < p.cap) *reinterpret_cast<uint2*>(p.pairs + 2 * g) = make_uint2(lo2, hi3);
+                    }
+                    ++slot;
+                }
+            }
+            if (t0 + BK_THREADS * BK_PAIR_CHUNK < P) out.maybe_flush(BK_OUT / 2);
         }
         out.maybe_flush(BK_OUT / 2);
     }
@@ -620,6 +720,15 @@ msm_status run_enumerate(msm_ctx* ctx, const uint64_t* S, int64_t n, int ell, in
             for (int b = lowest_kept + 1; b < k; ++b)
                 if ((Bm >> b) & 1ull) hi |= 1ull << b;
             cb.hi = hi;
+            cb.nhi = __builtin_popcountll(hi);
+            {
+                int slot = 0;
+                for (int b = 0; b < k && slot < MAXHI; ++b)
+                    if ((hi >> b) & 1ull) {
+                        for (int w = 0; w < MAXW; ++w) cb.himask[slot][w] = bm[(size_t)b * MAXW + w];
+                        ++slot;
+                    }
+            }
             combos.push_back(cb);
             int t = h - 1;
             while (t >= 0 && sel[t] == k - h + t) --t;
@@ -634,7 +743,7 @@ msm_status run_enumerate(msm_ctx* ctx, const uint64_t* S, int64_t n, int ell, in
     int r1 = 0;
     while (r1 < 13 && ((int64_t)1 << r1) * TARGET_BUCKET < n) ++r1;
     const int nb = 1 << r1;
-    const int sort_lo = 32 - r1 - 16;
+    const int sort_lo = 32 - r1 - BK_DIGIT;
     int T = 4096;
     while ((n + T - 1) / T > 65535) T *= 2;
     const int nt = (int)((n + T - 1) / T);
@@ -702,9 +811,12 @@ msm_status run_enumerate(msm_ctx* ctx, const uint64_t* S, int64_t n, int ell, in
         const int cc = std::min(Cg, C - c0);
         p.combos = d_combos + c0;
         hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, stream, d_ovfc, 4);
+        p.units = cc * nt;
+        const unsigned part_grid = (unsigned)((p.units + NUM_XCD - 1) / NUM_XCD * NUM_XCD);
         {
             msm::KernelTimer kt(ctx, stream, "k_part_count");
-            hipLaunchKernelGGL((k_part_count<W>), dim3(cc, nt), dim3(PART_THREADS), nb * sizeof(uint32_t), stream, p);
+            hipLaunchKernelGGL((k_part_count<W>), dim3(part_grid), dim3(PART_THREADS), nb * sizeof(uint32_t), stream,
+                               p);
         }
         {
             msm::KernelTimer kt(ctx, stream, "k_part_scan");
@@ -712,8 +824,8 @@ msm_status run_enumerate(msm_ctx* ctx, const uint64_t* S, int64_t n, int ell, in
         }
         {
             msm::KernelTimer kt(ctx, stream, "k_part_scatter");
-            hipLaunchKernelGGL((k_part_scatter<W>), dim3(cc, nt), dim3(PART_THREADS), nb * sizeof(uint32_t), stream,
-                               p);
+            hipLaunchKernelGGL((k_part_scatter<W>), dim3(part_grid), dim3(PART_THREADS), nb * sizeof(uint32_t),
+                               stream, p);
         }
         {
             msm::KernelTimer kt(ctx, stream, "k_bucket");

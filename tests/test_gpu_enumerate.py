@@ -76,13 +76,21 @@ def test_enumerate_tiny_n(msm, ctx, n):
     assert m == n * (n - 1) // 2
 
 
-@pytest.mark.parametrize("n", [1500, 5000])
+@pytest.mark.parametrize("n", [300, 1000, 1500, 5000])
 def test_enumerate_all_identical(msm, ctx, n):
     # Section 2.3: every pair is a solution; the single group exceeds the
     # LDS bucket and goes through the tile-against-tile path.
     S = np.tile(I.random_strings(1, 60, seed=13), (n, 1))
     m = check(msm, ctx, S, 60, 6, 2, cap_hint=n * (n - 1) // 2)
     assert m == n * (n - 1) // 2
+
+
+@pytest.mark.parametrize("flips", [0, 1, 2])
+def test_enumerate_identical_clusters(msm, ctx, flips):
+    # many groups of identical or nearly identical strings: runs where some
+    # blocks are constant over the whole run, others vary
+    S = I.random_strings(6000, 128, seed=61 + flips, n_seeds=40, flips=flips)
+    check(msm, ctx, S, 128, 8, 4, cap_hint=1 << 22)
 
 
 def test_enumerate_huge_clusters(msm, ctx):
