@@ -274,12 +274,13 @@ __device__ __forceinline__ bool pair_ok(const uint64_t* a, const uint64_t* b, co
     return ok;
 }
 
-// The same test with the masks of `hi` read from the combination (scalar
-// registers) when it has at most MAXHI blocks.
+// The same test, branch-free, with the masks of the first MAXHI blocks of
+// `hi` held in registers (hm). Combinations with more blocks in `hi` finish
+// with a loop over the block masks in LDS.
 template <int W>
 __device__ __forceinline__ bool pair_ok_fast(const uint64_t* a, const uint64_t* b, const Params& p,
-                                             const uint64_t (&keep)[W], const Combo* cb, uint64_t hi, int nhi,
-                                             const uint64_t* __restrict__ bmL)
+                                             const uint64_t (&keep)[W], const uint64_t (&hm)[MAXHI][W], int nhi,
+                                             uint64_t hi_rest, const uint64_t* __restrict__ bmL)
 {
     uint64_t x[W];
     int ham = 0;
@@ -291,26 +292,23 @@ __device__ __forceinline__ bool pair_ok_fast(const uint64_t* a, const uint64_t* 
         outside |= x[w] & keep[w];
     }
     bool ok = (ham <= p.h) & (outside == 0);
-    if (nhi <= MAXHI) {
 #pragma unroll
-        for (int s = 0; s < MAXHI; ++s) {
-            if (s < nhi) {
-                uint64_t any = 0;
-#pragma unroll
-                for (int w = 0; w < W; ++w) any |= x[w] & cb->himask[s][w];
-                ok &= any != 0;
-            }
-        }
-        return ok;
-    }
-    uint64_t need = hi;
-    while (need) {
-        const int blk = __builtin_ctzll(need);
-        need &= need - 1;
+    for (int s = 0; s < MAXHI; ++s) {
         uint64_t any = 0;
 #pragma unroll
-        for (int w = 0; w < W; ++w) any |= x[w] & bmL[blk * W + w];
-        ok &= any != 0;
+        for (int w = 0; w < W; ++w) any |= x[w] & hm[s][w];
+        ok &= (s >= nhi) | (any != 0);
+    }
+    if (hi_rest) {
+        uint64_t need = hi_rest;
+        while (need) {
+            const int blk = __builtin_ctzll(need);
+            need &= need - 1;
+            uint64_t any = 0;
+#pragma unroll
+            for (int w = 0; w < W; ++w) any |= x[w] & bmL[blk * W + w];
+            ok &= any != 0;
+        }
     }
     return ok;
 }
@@ -358,6 +356,14 @@ __global__ __launch_bounds__(BK_THREADS) void k_bucket(Params p)
     load_keep<W>(cb, keep);
     const uint64_t hi = cb->hi;
     const int nhi = cb->nhi;
+    uint64_t hm[MAXHI][W];
+#pragma unroll
+    for (int s2 = 0; s2 < MAXHI; ++s2)
+#pragma unroll
+        for (int w = 0; w < W; ++w) hm[s2][w] = cb->himask[s2][w];
+    // blocks of hi beyond the first MAXHI (tested from bmL)
+    uint64_t hi_rest = hi;
+    for (int s2 = 0; s2 < MAXHI && hi_rest; ++s2) hi_rest &= hi_rest - 1;
     for (int e = threadIdx.x; e < p.k * W; e += BK_THREADS) bmL[e] = p.bm[(e / W) * MAXW + (e % W)];
     for (int e = threadIdx.x; e < BK_BINS; e += BK_THREADS) hist[e] = 0;
     if (threadIdx.x == 0) ocnt = 0;
@@ -407,6 +413,16 @@ __global__ __launch_bounds__(BK_THREADS) void k_bucket(Params p)
             claimRun = 0;
             claimPair = 0;
         }
+        // Strings of the bucket's points, requested now and used after the
+        // histogram and the run claims, which hide the load latency.
+        uint64_t sreg[BK_MAXB][W];
+#pragma unroll
+        for (int b = 0; b < BK_MAXB; ++b) {
+            const int pos = threadIdx.x + b * BK_THREADS;
+            const uint64_t idx = pos < m ? (uint32_t)cur[b] : 0u;
+#pragma unroll
+            for (int w = 0; w < W; ++w) sreg[b][w] = pos < m ? p.S[idx * W + w] : 0ull;
+        }
 
         // histogram of the in-bucket digit; the returned count is the rank
         uint32_t dig[BK_MAXB], rank[BK_MAXB];
@@ -443,9 +459,8 @@ __global__ __launch_bounds__(BK_THREADS) void k_bucket(Params p)
             if (c[b] >= 2) {
                 const uint32_t q = binStart[dig[b]] + rank[b];
                 keysB[q] = cur[b];
-                const uint64_t idx = (uint32_t)cur[b];
 #pragma unroll
-                for (int w = 0; w < W; ++w) sl[q * W + w] = p.S[idx * W + w];
+                for (int w = 0; w < W; ++w) sl[q * W + w] = sreg[b][w];
             }
         }
         const uint32_t nruns = (uint32_t)(claimRun >> 32);
@@ -518,39 +533,46 @@ __global__ __launch_bounds__(BK_THREADS) void k_bucket(Params p)
                 L = liveL[r];
                 s0 = liveS[r];
                 const uint32_t u = t - liveP[r];
-                // row a of the upper triangle starts at a (2L - a - 1) / 2
+                // row a of the upper triangle starts at f(a) = a (2L - a - 1) / 2;
+                // the float root is within one of the integer answer
                 const float q = (float)(2 * L - 1);
                 int aa = (int)((q - sqrtf(q * q - 8.0f * (float)u)) * 0.5f);
                 aa = max(0, min(aa, L - 2));
-                while (aa < L - 2 && (uint32_t)((aa + 1) * (2 * L - aa - 2) / 2) <= u) ++aa;
-                while (aa > 0 && (uint32_t)(aa * (2 * L - aa - 1) / 2) > u) --aa;
+                if (aa < L - 2 && (uint32_t)((aa + 1) * (2 * L - aa - 2) / 2) <= u) ++aa;
+                if (aa > 0 && (uint32_t)(aa * (2 * L - aa - 1) / 2) > u) --aa;
                 a = aa;
                 bb = a + 1 + (int)(u - (uint32_t)(a * (2 * L - a - 1) / 2));
+            }
+            // positions of the chunk's candidates first, then the tests
+            int pa[BK_PAIR_CHUNK], pb[BK_PAIR_CHUNK];
+#pragma unroll
+            for (int q = 0; q < BK_PAIR_CHUNK; ++q) {
+                pa[q] = min(s0 + a, BK_CAP - 1);
+                pb[q] = min(s0 + bb, BK_CAP - 1);
+                ++bb;
+                const bool wrapRow = bb == L;
+                a += wrapRow;
+                bb = wrapRow ? a + 1 : bb;
+                if (wrapRow && a >= L - 1) {
+                    ++r;
+                    a = 0;
+                    bb = 1;
+                    const int rr = min(r, (int)nlive - 1);
+                    L = liveL[rr];
+                    s0 = liveS[rr];
+                }
             }
             uint32_t okbits = 0;
             uint32_t pi[BK_PAIR_CHUNK], pj[BK_PAIR_CHUNK];
 #pragma unroll
             for (int q = 0; q < BK_PAIR_CHUNK; ++q) {
                 const bool live = t + q < P;
-                const int pa = min(s0 + a, BK_CAP - 1), pb = min(s0 + bb, BK_CAP - 1);
-                const uint64_t ka = keysB[pa], kb = keysB[pb];
+                const uint64_t ka = keysB[pa[q]], kb = keysB[pb[q]];
                 pi[q] = (uint32_t)ka;
                 pj[q] = (uint32_t)kb;
-                const bool ok = live && (ka >> 32) == (kb >> 32) &&
-                                pair_ok_fast<W>(&sl[pa * W], &sl[pb * W], p, keep, cb, hi, nhi, bmL);
+                const bool ok = live & ((ka >> 32) == (kb >> 32)) &
+                                pair_ok_fast<W>(&sl[pa[q] * W], &sl[pb[q] * W], p, keep, hm, nhi, hi_rest, bmL);
                 okbits |= (uint32_t)ok << q;
-                if (++bb == L) {
-                    ++a;
-                    bb = a + 1;
-                    if (a >= L - 1) {
-                        ++r;
-                        a = 0;
-                        bb = 1;
-                        const int rr = min(r, (int)nlive - 1);
-                        L = liveL[rr];
-                        s0 = liveS[rr];
-                    }
-                }
             }
             // one append per lane per chunk: wave prefix of the counts, one
             // LDS atomic per wave
