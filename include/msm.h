@@ -56,6 +56,12 @@ typedef enum {
     MSM_COSINE = 1     /* Delta(x, y) = 1 - x.y / (||x|| ||y||), eq. (2); 1 if either is zero */
 } msm_metric;
 
+typedef enum {
+    MSM_F32 = 0,      /* FP32 products, FP32 accumulation (msm_project) */
+    MSM_BF16 = 1,     /* BF16 products, FP32 accumulation */
+    MSM_FP8_E4M3 = 2  /* FP8 e4m3 products of row/column-scaled copies, FP32 accumulation */
+} msm_dtype;
+
 typedef struct msm_ctx msm_ctx;
 
 /* Library version as 10000*major + 100*minor + patch. */
@@ -87,6 +93,25 @@ const char* msm_last_error(const msm_ctx* ctx);
  * with n > 0. Asynchronous: returns once the work is enqueued. */
 msm_status msm_project(msm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
                        const float* R, int32_t ell, uint64_t* S, void* stream);
+
+/* Random-projection LSH with low-precision products (eq. (3)). z = X R is
+ * estimated from BF16 copies of X and R, or from FP8 e4m3 copies scaled per
+ * row of X and per column of R (each to a largest magnitude of 240), with
+ * FP32 accumulation on the matrix cores; X is read as FP32 and converted on
+ * the fly. An entry whose estimate satisfies |z| < tau * ||x_i|| is
+ * recomputed as an FP32 dot product and takes its sign from that; every
+ * other entry takes the sign of the estimate. Outside the margin a sign can
+ * still differ from the exact one when the product error exceeds |z|.
+ *   X, R, S          as for msm_project
+ *   dtype            MSM_BF16 or MSM_FP8_E4M3
+ *   tau              margin relative to ||x_i|| (for example 2^-8), >= 0
+ *   n_recomputed     HOST, optional: number of entries recomputed in FP32;
+ *                    when non-NULL the call synchronises `stream`
+ * Errors: as msm_project, plus MSM_E_INVALID for another dtype or a negative
+ * or non-finite tau. */
+msm_status msm_project_lowp(msm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
+                            const float* R, int32_t ell, int32_t dtype, float tau, uint64_t* S,
+                            int64_t* n_recomputed, void* stream);
 
 /* All pairs within Hamming distance h, Sections 2.1-2.2 and eq. (1):
  *   { (i, j) : i < j, popcount(S_i xor S_j) <= h }

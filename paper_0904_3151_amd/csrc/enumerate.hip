@@ -766,8 +766,8 @@ msm_status run_enumerate(msm_ctx* ctx, const uint64_t* S, int64_t n, int ell, in
     while (r1 < 13 && ((int64_t)1 << r1) * TARGET_BUCKET < n) ++r1;
     const int nb = 1 << r1;
     const int sort_lo = 32 - r1 - BK_DIGIT;
-    int T = 4096;
-    while ((n + T - 1) / T > 65535) T *= 2;
+    int T = 4096;  // points per partition tile; at most 256 tiles per combination
+    while ((n + T - 1) / T > 256) T *= 2;
     const int nt = (int)((n + T - 1) / T);
 
     // Combinations per launch group, bounded by scratch size.

@@ -59,7 +59,12 @@ PAPER_SCALE = Workload("mixture-n1M-d128-l128-k8-h4", 1_000_000, 128, 128, 8, 4,
 LEARNED_SCALE = Workload("mixture-n2M-d128-l128-k8-h4", 2_000_000, 128, 128, 8, 4, 0.5,
                          "euclidean", 5000, (0.05, 0.3), 1005, 2005, 3005, subsample=50_000)
 
-WORKLOADS = {w.name: w for w in (TINY, PAPER_SCALE, LEARNED_SCALE)}
+# 4M L2-normalised nonnegative sparse rows (5% density, lognormal(0, 1)
+# values), d=256; l=240, k=10, h=8, cosine eps=0.2. Used by the precision form.
+PRECISION = Workload("sparse-n4M-d256-l240-k10-h8", 4_000_000, 256, 240, 10, 8, 0.2, "cosine",
+                     0, (0.0, 0.0), 1003, 2003, 3003, subsample=50_000, extra={"density": 0.05})
+
+WORKLOADS = {w.name: w for w in (TINY, PAPER_SCALE, LEARNED_SCALE, PRECISION)}
 
 
 def gaussian_mixture(n: int, d: int, n_centres: int, sigma, seed: int,
@@ -100,6 +105,23 @@ def gaussian_mixture(n: int, d: int, n_centres: int, sigma, seed: int,
     return X, labels
 
 
+def sparse_lognormal(n: int, d: int, density: float, seed: int, chunk: int = 1 << 18) -> np.ndarray:
+    """Rows with Bernoulli(density) support and lognormal(0, 1) values,
+    scaled to unit L2 norm; rows that draw no support stay all-zero."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    X = np.zeros((n, d), dtype=np.float32)
+    for a in range(0, n, chunk):
+        b = min(n, a + chunk)
+        mask = rng.random((b - a, d), dtype=np.float32) < density
+        block = np.zeros((b - a, d), dtype=np.float32)
+        block[mask] = rng.lognormal(0.0, 1.0, size=int(mask.sum())).astype(np.float32)
+        nrm = np.sqrt((block.astype(np.float64) ** 2).sum(axis=1)).astype(np.float32)
+        nz = nrm > 0
+        block[nz] /= nrm[nz, None]
+        X[a:b] = block
+    return X
+
+
 def projection_matrix(d: int, ell: int, seed: int) -> np.ndarray:
     """R in R^{d x ell} with i.i.d. N(0, 1) entries, float32, row-major.
 
@@ -112,6 +134,9 @@ def projection_matrix(d: int, ell: int, seed: int) -> np.ndarray:
 def workload_inputs(w: Workload, sigma_mode: str = "coord", n: int | None = None):
     """(X, R) for a named mixture workload; ``n`` truncates to the first rows."""
     n_use = w.n if n is None else int(n)
+    if "density" in w.extra:
+        X = sparse_lognormal(n_use, w.d, w.extra["density"], w.seed_data)
+        return X, projection_matrix(w.d, w.ell, w.seed_r)
     X, _ = gaussian_mixture(w.n, w.d, w.n_centres, w.sigma, w.seed_data, sigma_mode)
     if n_use != w.n:
         X = np.ascontiguousarray(X[:n_use])

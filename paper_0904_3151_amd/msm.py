@@ -32,10 +32,14 @@ MSM_E_HIP = -5
 
 EUCLIDEAN = 0
 COSINE = 1
+F32 = 0
+BF16 = 1
+FP8_E4M3 = 2
+DTYPES = {"f32": F32, "bf16": BF16, "fp8": FP8_E4M3, "fp8_e4m3": FP8_E4M3}
 METRICS = {"euclidean": EUCLIDEAN, "cosine": COSINE}
 
 EXPORTS = ("msm_version", "msm_create", "msm_destroy", "msm_last_error",
-           "msm_project", "msm_enumerate_pairs", "msm_verify", "msm_bruteforce_eps",
+           "msm_project", "msm_project_lowp", "msm_enumerate_pairs", "msm_verify", "msm_bruteforce_eps",
            "msm_profile_enable", "msm_profile_reset", "msm_profile_read")
 
 
@@ -65,6 +69,9 @@ def _load():
     lib.msm_last_error.restype = ctypes.c_char_p
     lib.msm_project.argtypes = [vp, vp, i64, i32, i64, vp, i32, vp, vp]
     lib.msm_project.restype = i32
+    lib.msm_project_lowp.argtypes = [vp, vp, i64, i32, i64, vp, i32, i32, ctypes.c_float, vp,
+                                     ctypes.POINTER(i64), vp]
+    lib.msm_project_lowp.restype = i32
     lib.msm_enumerate_pairs.argtypes = [vp, vp, i64, i32, i32, i32, vp, i64, ctypes.POINTER(i64), vp]
     lib.msm_enumerate_pairs.restype = i32
     lib.msm_verify.argtypes = [vp, vp, i64, i32, i64, vp, i64, i32, ctypes.c_float, vp, i64,
@@ -165,6 +172,30 @@ def msm_project(ctx: Context, X: torch.Tensor, R: torch.Tensor, S: torch.Tensor 
                           _ptr(S), _stream(stream))
     _check(ctx, st)
     return S
+
+
+def msm_project_lowp(ctx: Context, X: torch.Tensor, R: torch.Tensor, dtype="bf16", tau: float = 2.0 ** -8,
+                     S: torch.Tensor | None = None, count_recomputed: bool = False, stream=None):
+    """Sign strings from BF16 / FP8 products with FP32 margin recompute.
+
+    Returns S, or (S, n_recomputed) when ``count_recomputed``.
+    """
+    if isinstance(dtype, str):
+        dtype = DTYPES[dtype]
+    assert X.dtype == torch.float32 and X.dim() == 2 and X.stride(1) == 1 and X.is_cuda
+    assert R.dtype == torch.float32 and R.dim() == 2 and R.is_contiguous() and R.is_cuda
+    n, d = X.shape
+    ell = R.shape[1]
+    assert R.shape[0] == d
+    if S is None:
+        S = torch.empty((n, _words(ell)), dtype=torch.int64, device=X.device)
+    assert S.dtype == torch.int64 and S.is_contiguous() and S.shape == (n, _words(ell))
+    nre = ctypes.c_int64(0)
+    st = _lib.msm_project_lowp(ctx.handle, _ptr(X), n, d, X.stride(0) if n > 0 else d, _ptr(R), ell, int(dtype),
+                               float(tau), _ptr(S), ctypes.byref(nre) if count_recomputed else None,
+                               _stream(stream))
+    _check(ctx, st)
+    return (S, nre.value) if count_recomputed else S
 
 
 def msm_enumerate_pairs(ctx: Context, S: torch.Tensor, ell: int, k: int, h: int,
