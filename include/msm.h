@@ -136,6 +136,22 @@ msm_status msm_enumerate_pairs(msm_ctx* ctx, const uint64_t* S, int64_t n, int32
                                int32_t k, int32_t h, uint32_t* pairs, int64_t cap,
                                int64_t* m_out, void* stream);
 
+/* Union of the Hamming pairs of Q independent string pools, Section 4.1,
+ * eq. (5): E = E_1 u ... u E_Q with E_q = {(i, j) : i < j,
+ * popcount(S^q_i xor S^q_j) <= h}. Pool q is enumerated as in
+ * msm_enumerate_pairs, and, following the first acceleration trick of the
+ * paper's appendix, a pair found in pool q is written only if its Hamming
+ * distance exceeds h in every earlier pool g < q, so every pair of E is
+ * written exactly once.
+ *   S      DEVICE uint64[Q * n * W]   pools, replicate-major: string i of
+ *                                     pool q at S + (q * n + i) * W
+ *   Q      number of pools, 1 <= Q <= 4096
+ * Other arguments, limits and errors as for msm_enumerate_pairs (Q = 1 is
+ * the same call). Synchronises `stream`. */
+msm_status msm_enumerate_replicates(msm_ctx* ctx, const uint64_t* S, int64_t n, int32_t ell,
+                                    int32_t Q, int32_t k, int32_t h, uint32_t* pairs, int64_t cap,
+                                    int64_t* m_out, void* stream);
+
 /* Verification step of Section 4.1: keep the pairs of a list whose true
  * distance is at most eps (Definition 1.1). FP32 arithmetic: Euclidean
  * compares sum (x_t - y_t)^2 with eps^2; cosine compares eq. (2) with eps.

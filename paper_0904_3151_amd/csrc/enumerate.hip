@@ -73,7 +73,10 @@ struct Ovf {
 };
 
 struct Params {
-    const uint64_t* S;
+    const uint64_t* S;       // strings of the replicate being enumerated
+    const uint64_t* Sall;    // all replicates, replicate-major
+    uint64_t rep_stride;     // words between replicates (n * W)
+    int rep;                 // index of the replicate being enumerated
     int64_t n;
     const Combo* combos;     // combinations of this launch group
     const uint64_t* bm;      // [k][MAXW] block masks
@@ -311,6 +314,22 @@ __device__ __forceinline__ bool pair_ok_fast(const uint64_t* a, const uint64_t* 
         }
     }
     return ok;
+}
+
+// Cross-replicate dedup: a pair found in replicate q is written only if its
+// Hamming distance exceeds h in every earlier replicate g < q.
+template <int W>
+__device__ __forceinline__ bool far_in_earlier(const Params& p, uint32_t i, uint32_t j)
+{
+    for (int g = 0; g < p.rep; ++g) {
+        const uint64_t* a = p.Sall + (uint64_t)g * p.rep_stride + (uint64_t)i * W;
+        const uint64_t* b = p.Sall + (uint64_t)g * p.rep_stride + (uint64_t)j * W;
+        int ham = 0;
+#pragma unroll
+        for (int w = 0; w < W; ++w) ham += __popcll((a[w] ^ b[w]) & p.valid[w]);
+        if (ham <= p.h) return false;
+    }
+    return true;
 }
 
 // -------------------------------------------------------------------------
@@ -574,6 +593,11 @@ __global__ __launch_bounds__(BK_THREADS) void k_bucket(Params p)
                                 pair_ok_fast<W>(&sl[pa[q] * W], &sl[pb[q] * W], p, keep, hm, nhi, hi_rest, bmL);
                 okbits |= (uint32_t)ok << q;
             }
+            if (p.rep > 0 && okbits) {
+#pragma unroll
+                for (int q = 0; q < BK_PAIR_CHUNK; ++q)
+                    if (((okbits >> q) & 1u) && !far_in_earlier<W>(p, pi[q], pj[q])) okbits &= ~(1u << q);
+            }
             // one append per lane per chunk: wave prefix of the counts, one
             // LDS atomic per wave
             const uint32_t nmine = (uint32_t)__popc(okbits);
@@ -676,6 +700,7 @@ __global__ __launch_bounds__(BIG_TILE) void k_big(Params p, const Ovf* __restric
         bool ok = rv && (!diag || jj > (int)threadIdx.x) && (uint32_t)(kc >> 32) == mine;
         if (ok) ok = pair_ok<W>(&sR[threadIdx.x * W], &sC[jj * W], p, keep, hi, bmL);
         const uint32_t jv = (uint32_t)kc;
+        if (ok && p.rep > 0) ok = far_in_earlier<W>(p, ii, jv);
         out.push(ok, ii < jv ? ii : jv, ii < jv ? jv : ii);
         if ((jj & 7) == 7) out.maybe_flush(BK_OUT / 2);
     }
@@ -706,7 +731,7 @@ int64_t binom(int a, int b)
 }
 
 template <int W>
-msm_status run_enumerate(msm_ctx* ctx, const uint64_t* S, int64_t n, int ell, int k, int h,
+msm_status run_enumerate(msm_ctx* ctx, const uint64_t* S, int64_t n, int ell, int Q, int k, int h,
                          uint32_t* pairs, int64_t cap, int64_t* m_out, hipStream_t stream)
 {
     // Blocks of nearly equal length: the first ell mod k get one extra bit.
@@ -808,6 +833,9 @@ msm_status run_enumerate(msm_ctx* ctx, const uint64_t* S, int64_t n, int ell, in
 
     Params p{};
     p.S = S;
+    p.Sall = S;
+    p.rep_stride = (uint64_t)n * W;
+    p.rep = 0;
     p.n = n;
     p.bm = d_bm;
     p.k = k;
@@ -829,6 +857,9 @@ msm_status run_enumerate(msm_ctx* ctx, const uint64_t* S, int64_t n, int ell, in
 
     std::vector<Ovf> hovf;
     std::vector<uint64_t> htile;
+    for (int rep = 0; rep < Q; ++rep) {
+    p.rep = rep;
+    p.S = S + (uint64_t)rep * p.rep_stride;
     for (int c0 = 0; c0 < C; c0 += Cg) {
         const int cc = std::min(Cg, C - c0);
         p.combos = d_combos + c0;
@@ -879,6 +910,7 @@ msm_status run_enumerate(msm_ctx* ctx, const uint64_t* S, int64_t n, int ell, in
             MSM_HIP(ctx, hipGetLastError());
         }
     }
+    }
     MSM_HIP(ctx, hipMemcpyAsync(ctx->host_words, d_counter, sizeof(unsigned long long), hipMemcpyDeviceToHost,
                                 stream));
     MSM_HIP(ctx, hipStreamSynchronize(stream));
@@ -892,37 +924,49 @@ msm_status run_enumerate(msm_ctx* ctx, const uint64_t* S, int64_t n, int ell, in
 
 }  // namespace
 
-extern "C" msm_status msm_enumerate_pairs(msm_ctx* ctx, const uint64_t* S, int64_t n, int32_t ell,
-                                          int32_t k, int32_t h, uint32_t* pairs, int64_t cap,
-                                          int64_t* m_out, void* stream)
+static msm_status enumerate_entry(const char* fn, msm_ctx* ctx, const uint64_t* S, int64_t n, int32_t ell,
+                                  int32_t Q, int32_t k, int32_t h, uint32_t* pairs, int64_t cap, int64_t* m_out,
+                                  void* stream)
 {
-    if (!ctx) return msm::fail(nullptr, MSM_E_INVALID, "msm_enumerate_pairs: ctx is NULL");
+    if (!ctx) return msm::fail(nullptr, MSM_E_INVALID, "%s: ctx is NULL", fn);
     ctx->err.clear();
-    if (!m_out) return msm::fail(ctx, MSM_E_INVALID, "msm_enumerate_pairs: m_out is NULL");
+    if (!m_out) return msm::fail(ctx, MSM_E_INVALID, "%s: m_out is NULL", fn);
     *m_out = 0;
-    if (n < 0 || n > 0xFFFFFFFFll)
-        return msm::fail(ctx, MSM_E_INVALID, "msm_enumerate_pairs: n=%lld out of range", (long long)n);
-    if (ell < 1 || ell > 256)
-        return msm::fail(ctx, MSM_E_INVALID, "msm_enumerate_pairs: ell=%d not in [1, 256]", ell);
+    if (n < 0 || n > 0xFFFFFFFFll) return msm::fail(ctx, MSM_E_INVALID, "%s: n=%lld out of range", fn, (long long)n);
+    if (ell < 1 || ell > 256) return msm::fail(ctx, MSM_E_INVALID, "%s: ell=%d not in [1, 256]", fn, ell);
+    if (Q < 1 || Q > 4096) return msm::fail(ctx, MSM_E_INVALID, "%s: Q=%d not in [1, 4096]", fn, Q);
     if (h < 0 || k <= h || k > ell)
-        return msm::fail(ctx, MSM_E_INVALID, "msm_enumerate_pairs: need 0 <= h < k <= ell (k=%d, h=%d)", k, h);
-    if (k > MAXK)
-        return msm::fail(ctx, MSM_E_UNSUPPORTED, "msm_enumerate_pairs: k=%d above %d", k, MAXK);
+        return msm::fail(ctx, MSM_E_INVALID, "%s: need 0 <= h < k <= ell (k=%d, h=%d)", fn, k, h);
+    if (k > MAXK) return msm::fail(ctx, MSM_E_UNSUPPORTED, "%s: k=%d above %d", fn, k, MAXK);
     if (binom(k, h) > 65536)
-        return msm::fail(ctx, MSM_E_UNSUPPORTED, "msm_enumerate_pairs: C(%d, %d) combinations above 65536", k, h);
-    if (cap < 0) return msm::fail(ctx, MSM_E_INVALID, "msm_enumerate_pairs: cap < 0");
-    if (cap > 0 && !pairs) return msm::fail(ctx, MSM_E_INVALID, "msm_enumerate_pairs: pairs is NULL with cap > 0");
+        return msm::fail(ctx, MSM_E_UNSUPPORTED, "%s: C(%d, %d) combinations above 65536", fn, k, h);
+    if (cap < 0) return msm::fail(ctx, MSM_E_INVALID, "%s: cap < 0", fn);
+    if (cap > 0 && !pairs) return msm::fail(ctx, MSM_E_INVALID, "%s: pairs is NULL with cap > 0", fn);
     if (pairs && (reinterpret_cast<uintptr_t>(pairs) & 7))
-        return msm::fail(ctx, MSM_E_INVALID, "msm_enumerate_pairs: pairs must be 8-byte aligned");
+        return msm::fail(ctx, MSM_E_INVALID, "%s: pairs must be 8-byte aligned", fn);
     if (n < 2) return MSM_OK;
-    if (!S) return msm::fail(ctx, MSM_E_INVALID, "msm_enumerate_pairs: S is NULL");
+    if (!S) return msm::fail(ctx, MSM_E_INVALID, "%s: S is NULL", fn);
     msm_status st = msm::use_device(ctx);
     if (st != MSM_OK) return st;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     switch ((ell + 63) / 64) {
-        case 1: return run_enumerate<1>(ctx, S, n, ell, k, h, pairs, cap, m_out, s);
-        case 2: return run_enumerate<2>(ctx, S, n, ell, k, h, pairs, cap, m_out, s);
-        case 3: return run_enumerate<3>(ctx, S, n, ell, k, h, pairs, cap, m_out, s);
-        default: return run_enumerate<4>(ctx, S, n, ell, k, h, pairs, cap, m_out, s);
+        case 1: return run_enumerate<1>(ctx, S, n, ell, Q, k, h, pairs, cap, m_out, s);
+        case 2: return run_enumerate<2>(ctx, S, n, ell, Q, k, h, pairs, cap, m_out, s);
+        case 3: return run_enumerate<3>(ctx, S, n, ell, Q, k, h, pairs, cap, m_out, s);
+        default: return run_enumerate<4>(ctx, S, n, ell, Q, k, h, pairs, cap, m_out, s);
     }
+}
+
+extern "C" msm_status msm_enumerate_pairs(msm_ctx* ctx, const uint64_t* S, int64_t n, int32_t ell,
+                                          int32_t k, int32_t h, uint32_t* pairs, int64_t cap,
+                                          int64_t* m_out, void* stream)
+{
+    return enumerate_entry("msm_enumerate_pairs", ctx, S, n, ell, 1, k, h, pairs, cap, m_out, stream);
+}
+
+extern "C" msm_status msm_enumerate_replicates(msm_ctx* ctx, const uint64_t* S, int64_t n, int32_t ell,
+                                               int32_t Q, int32_t k, int32_t h, uint32_t* pairs, int64_t cap,
+                                               int64_t* m_out, void* stream)
+{
+    return enumerate_entry("msm_enumerate_replicates", ctx, S, n, ell, Q, k, h, pairs, cap, m_out, stream);
 }

@@ -131,6 +131,13 @@ def projection_matrix(d: int, ell: int, seed: int) -> np.ndarray:
     return rng.standard_normal((d, ell), dtype=np.float32)
 
 
+def projection_matrices(d: int, ell: int, Q: int, seed: int) -> np.ndarray:
+    """Q independent projection matrices (Q, d, ell), one per string pool
+    (Section 4.1). Pool 0 uses `seed` itself, so it equals
+    projection_matrix(d, ell, seed); pool q uses seed + 100 q."""
+    return np.stack([projection_matrix(d, ell, seed + 100 * q) for q in range(Q)])
+
+
 def workload_inputs(w: Workload, sigma_mode: str = "coord", n: int | None = None):
     """(X, R) for a named mixture workload; ``n`` truncates to the first rows."""
     n_use = w.n if n is None else int(n)

@@ -39,7 +39,8 @@ DTYPES = {"f32": F32, "bf16": BF16, "fp8": FP8_E4M3, "fp8_e4m3": FP8_E4M3}
 METRICS = {"euclidean": EUCLIDEAN, "cosine": COSINE}
 
 EXPORTS = ("msm_version", "msm_create", "msm_destroy", "msm_last_error",
-           "msm_project", "msm_project_lowp", "msm_enumerate_pairs", "msm_verify", "msm_bruteforce_eps",
+           "msm_project", "msm_project_lowp", "msm_enumerate_pairs", "msm_enumerate_replicates",
+           "msm_verify", "msm_bruteforce_eps",
            "msm_profile_enable", "msm_profile_reset", "msm_profile_read")
 
 
@@ -74,6 +75,8 @@ def _load():
     lib.msm_project_lowp.restype = i32
     lib.msm_enumerate_pairs.argtypes = [vp, vp, i64, i32, i32, i32, vp, i64, ctypes.POINTER(i64), vp]
     lib.msm_enumerate_pairs.restype = i32
+    lib.msm_enumerate_replicates.argtypes = [vp, vp, i64, i32, i32, i32, i32, vp, i64, ctypes.POINTER(i64), vp]
+    lib.msm_enumerate_replicates.restype = i32
     lib.msm_verify.argtypes = [vp, vp, i64, i32, i64, vp, i64, i32, ctypes.c_float, vp, i64,
                                ctypes.POINTER(i64), vp]
     lib.msm_verify.restype = i32
@@ -223,6 +226,29 @@ def msm_enumerate_pairs(ctx: Context, S: torch.Tensor, ell: int, k: int, h: int,
     return (pairs[: m.value] if pairs is not None else None), m.value
 
 
+def msm_enumerate_replicates(ctx: Context, S: torch.Tensor, ell: int, k: int, h: int,
+                             pairs: torch.Tensor | None = None, cap: int | None = None, stream=None):
+    """Union of the Hamming pairs of Q pools (eq. (5)), each pair once.
+
+    S is int64 (Q, n, W). Returns (pairs[:m], m) like msm_enumerate_pairs.
+    """
+    assert S.dtype == torch.int64 and S.dim() == 3 and S.is_contiguous() and S.is_cuda
+    Q, n, Wd = S.shape
+    assert Wd == _words(ell)
+    if pairs is None:
+        cap = 0 if cap is None else int(cap)
+        if cap > 0:
+            pairs = torch.empty((cap, 2), dtype=torch.int32, device=S.device)
+    else:
+        assert pairs.dtype == torch.int32 and pairs.is_contiguous() and pairs.dim() == 2
+        cap = pairs.shape[0] if cap is None else int(cap)
+    m = ctypes.c_int64(0)
+    st = _lib.msm_enumerate_replicates(ctx.handle, _ptr(S), n, int(ell), Q, int(k), int(h), _ptr(pairs), cap,
+                                       ctypes.byref(m), _stream(stream))
+    _check(ctx, st, m.value)
+    return (pairs[: m.value] if pairs is not None else None), m.value
+
+
 def msm_verify(ctx: Context, X: torch.Tensor, pairs: torch.Tensor, metric, eps: float,
                out: torch.Tensor | None = None, cap: int | None = None, stream=None):
     """Pairs of ``pairs`` whose distance is at most eps (Section 4.1).
@@ -308,11 +334,13 @@ def msm_profile_read(ctx: Context) -> dict:
 
 def enumerate_pairs(ctx: Context, S: torch.Tensor, ell: int, k: int, h: int, cap_hint: int = 1 << 20,
                     stream=None):
-    """msm_enumerate_pairs with an output buffer that is grown on demand."""
+    """msm_enumerate_pairs (S of shape (n, W)) or msm_enumerate_replicates
+    (S of shape (Q, n, W)) with an output buffer that is grown on demand."""
+    fn = msm_enumerate_replicates if S.dim() == 3 else msm_enumerate_pairs
     cap = max(1, int(cap_hint))
     while True:
         try:
-            return msm_enumerate_pairs(ctx, S, ell, k, h, cap=cap, stream=stream)
+            return fn(ctx, S, ell, k, h, cap=cap, stream=stream)
         except MSMError as e:
             if e.status != MSM_E_CAPACITY:
                 raise
