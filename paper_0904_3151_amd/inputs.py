@@ -138,6 +138,15 @@ def projection_matrices(d: int, ell: int, Q: int, seed: int) -> np.ndarray:
     return np.stack([projection_matrix(d, ell, seed + 100 * q) for q in range(Q)])
 
 
+def mlp_initial_parameters(d: int, hid: int, ell: int, seed: int) -> np.ndarray:
+    """Initial weights of the learned projection, packed FP32
+    [W1 (d x hid) | b1 | W2 (hid x ell) | b2]: W ~ N(0, 2 / fan_in), b = 0."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    W1 = rng.standard_normal((d, hid)) * np.sqrt(2.0 / d)
+    W2 = rng.standard_normal((hid, ell)) * np.sqrt(2.0 / hid)
+    return np.concatenate([W1.ravel(), np.zeros(hid), W2.ravel(), np.zeros(ell)]).astype(np.float32)
+
+
 def workload_inputs(w: Workload, sigma_mode: str = "coord", n: int | None = None):
     """(X, R) for a named mixture workload; ``n`` truncates to the first rows."""
     n_use = w.n if n is None else int(n)
