@@ -184,6 +184,68 @@ msm_status msm_bruteforce_eps(msm_ctx* ctx, const float* X, int64_t n, int32_t d
                               int32_t metric, float eps, uint32_t* out, int64_t cap,
                               int64_t* m_out, void* stream);
 
+/* Learned projection: a two-layer network in place of the random
+ * projection, the non-random hashing named in Section 6. For a row x:
+ *   a1 = x W1 + b1,  g = GELU(a1) = a1 (1 + erf(a1 / sqrt 2)) / 2,
+ *   a2 = g W2 + b2,  u = tanh(a2),  bit c of S_i = 1 iff a2_c > 0.
+ * Products use BF16 copies of the operands with FP32 accumulation on the
+ * matrix cores; biases, activations and the loss are FP32.
+ *   params DEVICE float[d*hid + hid + hid*ell + ell], packed row-major as
+ *          [W1 (d x hid) | b1 (hid) | W2 (hid x ell) | b2 (ell)]
+ * The strings can be used wherever msm_project's are.
+ *   X, S   as for msm_project (S fully written, padding bits 0)
+ * Limits: n >= 0, 1 <= d, ldx >= d, 1 <= hid <= 65536, 1 <= ell <= 256.
+ * Errors: MSM_E_INVALID for sizes or NULL pointers with n > 0; MSM_E_NOMEM
+ * when scratch for the BF16 weights cannot be allocated. Asynchronous. */
+msm_status msm_project_mlp(msm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
+                           const float* params, int32_t hid, int32_t ell, uint64_t* S, void* stream);
+
+/* Loss and gradient of the learned projection over B labelled pairs. With
+ * D = (ell - u_i . u_j) / 2 (the Hamming distance of the sign strings when
+ * u is +-1), the loss is the mean over the pairs of
+ *   y relu(D - h/2)^2 + (1 - y) relu(3h - D)^2
+ *     + lam (sum_c (1 - |u_ic|)^2 + sum_c (1 - |u_jc|)^2),
+ * pulling epsilon-pairs (y = 1) inside the MSM threshold h and pushing other
+ * pairs beyond 3h, with a term that drives u towards +-1.
+ *   pairs  DEVICE uint32[2 * B]     (i, j) row indices into X, each < n
+ *   labels DEVICE float[B]          y in [0, 1]
+ *   grad   DEVICE float[#params]    d loss / d params, packed like params
+ *   loss_out HOST float, optional   the loss
+ * Errors: MSM_E_INVALID for sizes, NULL pointers, B outside [1, 2^24],
+ * negative or non-finite h or lam, or a pair index >= n (nothing is
+ * computed then). Synchronises `stream`. */
+msm_status msm_mlp_loss_grad(msm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
+                             const float* params, int32_t hid, int32_t ell, const uint32_t* pairs,
+                             const float* labels, int32_t B, float h, float lam, float* grad,
+                             float* loss_out, void* stream);
+
+/* One Adam step (Kingma and Ba, 2015) on `count` FP32 parameters:
+ *   m = b1 m + (1 - b1) g,  v = b2 v + (1 - b2) g^2,
+ *   p -= lr (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps).
+ * params, m, v are updated in place (DEVICE, count floats each); step >= 1
+ * counts from 1. Errors: MSM_E_INVALID for NULL pointers with count > 0,
+ * step < 1, lr < 0, b1 or b2 outside [0, 1), eps <= 0. Asynchronous. */
+msm_status msm_mlp_adam(msm_ctx* ctx, float* params, const float* grad, float* m, float* v,
+                        int64_t count, int64_t step, float lr, float beta1, float beta2, float eps,
+                        void* stream);
+
+/* `steps` training steps of the learned projection, each msm_mlp_loss_grad
+ * on the next `batch` pairs of the list followed by msm_mlp_adam (beta1 0.9,
+ * beta2 0.999, eps 1e-8) with Adam step numbers first_step, first_step + 1,
+ * ... A batch that would run past the end of the list starts again at pair
+ * 0, so the caller shuffles the list. Batches hold min(batch, npairs) pairs.
+ *   params, m, v DEVICE float[#params], updated in place
+ *   pairs, labels as for msm_mlp_loss_grad, npairs entries
+ *   losses HOST float[steps], optional: the loss of every step
+ * Errors as for msm_mlp_loss_grad (all pair indices are checked once before
+ * the first step). Synchronises `stream` when losses is non-NULL or a pair
+ * index is checked (always). */
+msm_status msm_mlp_train(msm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
+                         float* params, float* m, float* v, int32_t hid, int32_t ell,
+                         const uint32_t* pairs, const float* labels, int64_t npairs, int32_t batch,
+                         int64_t steps, int64_t first_step, float lr, float h, float lam,
+                         float* losses, void* stream);
+
 /* Per-kernel timing. While enabled, every kernel launch of the context is
  * bracketed by two HIP events on its stream (a few microseconds of overhead
  * per launch). Timings accumulate per kernel name until msm_profile_reset. */

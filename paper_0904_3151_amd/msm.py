@@ -41,6 +41,7 @@ METRICS = {"euclidean": EUCLIDEAN, "cosine": COSINE}
 EXPORTS = ("msm_version", "msm_create", "msm_destroy", "msm_last_error",
            "msm_project", "msm_project_lowp", "msm_enumerate_pairs", "msm_enumerate_replicates",
            "msm_verify", "msm_bruteforce_eps",
+           "msm_project_mlp", "msm_mlp_loss_grad", "msm_mlp_adam", "msm_mlp_train",
            "msm_profile_enable", "msm_profile_reset", "msm_profile_read")
 
 
@@ -83,6 +84,17 @@ def _load():
     lib.msm_bruteforce_eps.argtypes = [vp, vp, i64, i32, i64, i32, ctypes.c_float, vp, i64,
                                        ctypes.POINTER(i64), vp]
     lib.msm_bruteforce_eps.restype = i32
+    f32 = ctypes.c_float
+    lib.msm_project_mlp.argtypes = [vp, vp, i64, i32, i64, vp, i32, i32, vp, vp]
+    lib.msm_project_mlp.restype = i32
+    lib.msm_mlp_loss_grad.argtypes = [vp, vp, i64, i32, i64, vp, i32, i32, vp, vp, i32, f32, f32, vp,
+                                      ctypes.POINTER(f32), vp]
+    lib.msm_mlp_loss_grad.restype = i32
+    lib.msm_mlp_adam.argtypes = [vp, vp, vp, vp, vp, i64, i64, f32, f32, f32, f32, vp]
+    lib.msm_mlp_adam.restype = i32
+    lib.msm_mlp_train.argtypes = [vp, vp, i64, i32, i64, vp, vp, vp, i32, i32, vp, vp, i64, i32, i64, i64,
+                                  f32, f32, f32, ctypes.POINTER(f32), vp]
+    lib.msm_mlp_train.restype = i32
     lib.msm_profile_enable.argtypes = [vp, i32]
     lib.msm_profile_enable.restype = i32
     lib.msm_profile_reset.argtypes = [vp]
@@ -310,6 +322,85 @@ def bruteforce_eps(ctx: Context, X: torch.Tensor, metric, eps: float, cap_hint: 
             if e.status != MSM_E_CAPACITY:
                 raise
             cap = int(e.required)
+
+
+def mlp_param_count(d: int, hid: int, ell: int) -> int:
+    """Length of the packed parameter vector [W1 | b1 | W2 | b2]."""
+    return d * hid + hid + hid * ell + ell
+
+
+def _check_params(params, d, hid, ell):
+    assert params.dtype == torch.float32 and params.is_cuda and params.is_contiguous()
+    assert params.numel() == mlp_param_count(d, hid, ell), "params has the wrong length for (d, hid, ell)"
+
+
+def msm_project_mlp(ctx: Context, X: torch.Tensor, params: torch.Tensor, hid: int, ell: int,
+                    S: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Sign strings of the learned projection (signs of a2); returns S as int64 (n, W)."""
+    assert X.dtype == torch.float32 and X.dim() == 2 and X.stride(1) == 1 and X.is_cuda
+    n, d = X.shape
+    _check_params(params, d, hid, ell)
+    if S is None:
+        S = torch.empty((n, _words(ell)), dtype=torch.int64, device=X.device)
+    assert S.dtype == torch.int64 and S.is_contiguous() and S.shape == (n, _words(ell))
+    st = _lib.msm_project_mlp(ctx.handle, _ptr(X), n, d, X.stride(0) if n > 0 else d, _ptr(params), hid, ell,
+                              _ptr(S), _stream(stream))
+    _check(ctx, st)
+    return S
+
+
+def _check_pairs(pairs, labels):
+    assert pairs.dtype == torch.int32 and pairs.is_cuda and pairs.is_contiguous() and pairs.dim() == 2
+    assert pairs.shape[1] == 2
+    assert labels.dtype == torch.float32 and labels.is_cuda and labels.is_contiguous()
+    assert labels.numel() == pairs.shape[0]
+
+
+def msm_mlp_loss_grad(ctx: Context, X: torch.Tensor, params: torch.Tensor, hid: int, ell: int,
+                      pairs: torch.Tensor, labels: torch.Tensor, h: float, lam: float,
+                      grad: torch.Tensor | None = None, stream=None):
+    """(loss, grad) of the pair loss over pairs (int32 (B, 2)) with labels (float32 (B,))."""
+    assert X.dtype == torch.float32 and X.dim() == 2 and X.stride(1) == 1 and X.is_cuda
+    n, d = X.shape
+    _check_params(params, d, hid, ell)
+    _check_pairs(pairs, labels)
+    if grad is None:
+        grad = torch.empty_like(params)
+    assert grad.dtype == torch.float32 and grad.is_contiguous() and grad.numel() == params.numel()
+    loss = ctypes.c_float(0.0)
+    st = _lib.msm_mlp_loss_grad(ctx.handle, _ptr(X), n, d, X.stride(0) if n > 0 else d, _ptr(params), hid, ell,
+                                _ptr(pairs), _ptr(labels), pairs.shape[0], float(h), float(lam), _ptr(grad),
+                                ctypes.byref(loss), _stream(stream))
+    _check(ctx, st)
+    return loss.value, grad
+
+
+def msm_mlp_adam(ctx: Context, params: torch.Tensor, grad: torch.Tensor, m: torch.Tensor, v: torch.Tensor,
+                 step: int, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8, stream=None):
+    """One Adam step on params, m, v in place."""
+    for t in (params, grad, m, v):
+        assert t.dtype == torch.float32 and t.is_cuda and t.is_contiguous() and t.numel() == params.numel()
+    st = _lib.msm_mlp_adam(ctx.handle, _ptr(params), _ptr(grad), _ptr(m), _ptr(v), params.numel(), int(step),
+                           float(lr), float(beta1), float(beta2), float(eps), _stream(stream))
+    _check(ctx, st)
+
+
+def msm_mlp_train(ctx: Context, X: torch.Tensor, params: torch.Tensor, m: torch.Tensor, v: torch.Tensor,
+                  hid: int, ell: int, pairs: torch.Tensor, labels: torch.Tensor, batch: int, steps: int,
+                  first_step: int, lr: float, h: float, lam: float, stream=None):
+    """``steps`` loss/gradient + Adam steps over consecutive batches; returns the losses."""
+    assert X.dtype == torch.float32 and X.dim() == 2 and X.stride(1) == 1 and X.is_cuda
+    n, d = X.shape
+    _check_params(params, d, hid, ell)
+    _check_pairs(pairs, labels)
+    for t in (m, v):
+        assert t.dtype == torch.float32 and t.is_cuda and t.is_contiguous() and t.numel() == params.numel()
+    losses = (ctypes.c_float * max(1, int(steps)))()
+    st = _lib.msm_mlp_train(ctx.handle, _ptr(X), n, d, X.stride(0) if n > 0 else d, _ptr(params), _ptr(m), _ptr(v),
+                            hid, ell, _ptr(pairs), _ptr(labels), pairs.shape[0], int(batch), int(steps),
+                            int(first_step), float(lr), float(h), float(lam), losses, _stream(stream))
+    _check(ctx, st)
+    return [float(losses[i]) for i in range(int(steps))]
 
 
 def msm_profile_enable(ctx: Context, enable: bool = True):
