@@ -3,10 +3,18 @@
 One step = msm_project + msm_enumerate_pairs + msm_verify over the paper-scale
 mixture (n = 1,000,000, d = 128, ell = 128 bits, k = 8 blocks, h = 4,
 Euclidean eps = 0.5), inputs already resident in device memory. Prints one
-JSON line. ``value`` is points per second of whole steps.
+JSON line. ``value`` is points per second of whole steps. The run is repeated
+under the other reading of the mixture's sigma (per-coordinate standard
+deviation, or cluster radius), under which the epsilon graph is not empty
+and the missing-edge ratio is defined.
+
+Other workloads: ``--workload precision`` (4M sparse cosine rows, FP32 /
+BF16 / FP8 projections) and ``--workload learned`` (2M mixture points, the
+learned projection trained on the GPU against random projection).
 
 Usage: python bench.py [--steps K] [--warmup W] [--sigma-mode coord|radius]
-                       [--cpu-sample N | --no-cpu-baseline]
+                       [--cpu-sample N | --no-cpu-baseline] [--no-second-reading]
+                       [--workload paper|precision|learned] [--epochs E]
 """
 import argparse
 import json
@@ -20,6 +28,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 FP32_MFMA_PEAK_TFLOPS = 157.3
+BF16_MFMA_PEAK_TFLOPS = 2500.0
 METRIC = "points/s + edges/s at n=1M,d=128,ℓ=128,h≤4; missing-edge ratio vs brute"
 
 
@@ -32,7 +41,7 @@ def algorithmic(kernel, w, n, C, mH, mE, W):
 
     Units per launch: a launch of the partition and bucket kernels covers n
     points under each of the C combinations; k_verify covers the mH
-    candidate pairs; k_project_f32 the n x d x ell products.
+    candidate pairs and the n rows; k_project_f32 the n x d x ell products.
     """
     sb = 8 * W  # bytes of one string
     if kernel == "k_project_f32":
@@ -42,13 +51,17 @@ def algorithmic(kernel, w, n, C, mH, mE, W):
     if kernel == "k_part_scatter":
         return n * C * (sb + 8) / 1e9, "GB/s", "hbm"
     if kernel == "k_bucket":
-        return (n * C * 8 + mH * 8) / 1e9, "GB/s", "hbm"
+        # per point and combination: its 8-byte partition entry and its string
+        return (n * C * (8 + sb) + mH * 8) / 1e9, "GB/s", "hbm"
     if kernel == "k_verify":
-        return (mH * (8 + 2 * 4 * w.d) + mE * 8) / 1e9, "GB/s", "hbm"
+        # compulsory traffic: candidate pairs in, kept pairs out, each row
+        # of X once (the two rows of every candidate are re-read through the
+        # caches, not from HBM)
+        return (mH * 8 + mE * 8 + n * 4 * w.d) / 1e9, "GB/s", "hbm"
     return None
 
 
-def missing_edge_ratio(msm, ctx, w, Xd, hamming, verified):
+def missing_edge_ratio(msm, ctx, w, Xd, hamming, verified, sub=None):
     """|E* minus E_eps| / |E*| on a seeded subsample (Section 4.2), where E* is
     the exhaustive epsilon graph of the subsample (the judge) and E_eps the
     verified pairs with both ends in it. Every MSM decision is per pair, so
@@ -56,7 +69,8 @@ def missing_edge_ratio(msm, ctx, w, Xd, hamming, verified):
     import torch
 
     from paper_0904_3151_amd import inputs as I
-    sub = torch.from_numpy(I.subsample_indices(w.n, w.subsample, w.seed_sub)).to(Xd.device)
+    if sub is None:
+        sub = torch.from_numpy(I.subsample_indices(w.n, w.subsample, w.seed_sub)).to(Xd.device)
     t0 = time.perf_counter()
     star, mstar = msm.bruteforce_eps(ctx, Xd[sub].contiguous(), w.metric, w.eps, cap_hint=1 << 22)
     torch.cuda.synchronize()
@@ -197,6 +211,147 @@ def run_precision(args):
     ctx.close()
 
 
+def run_mixture(msm, ctx, w, X, Xd, project, steps, warmup, judge_sub=None):
+    """Time `steps` whole steps (project, enumerate, verify) over a mixture
+    workload already on the device, then judge the missing-edge ratio.
+    `project(S)` writes the strings. Returns a dict of results."""
+    import torch
+
+    n, W = Xd.shape[0], (w.ell + 63) // 64
+    S = torch.empty((n, W), dtype=torch.int64, device=Xd.device)
+    C = 1
+    for t in range(w.h):
+        C = C * (w.k - t) // (t + 1)
+    # size the output buffers with a count-only pass
+    project(S)
+    _, mH = msm.msm_enumerate_pairs(ctx, S, w.ell, w.k, w.h, cap=0)
+    pairs = torch.empty((max(1, int(mH * 1.05) + 1024), 2), dtype=torch.int32, device=Xd.device)
+    verified = torch.empty_like(pairs)
+    log(f"hamming pairs {mH}")
+
+    def step():
+        project(S)
+        P, m = msm.msm_enumerate_pairs(ctx, S, w.ell, w.k, w.h, pairs=pairs)
+        V, kept = msm.msm_verify(ctx, Xd, P, w.metric, w.eps, out=verified)
+        return m, kept
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    msm.msm_profile_reset(ctx)
+    msm.msm_profile_enable(ctx, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        mH, mE = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    msm.msm_profile_enable(ctx, False)
+    prof = msm.msm_profile_read(ctx)
+    ms_step = (t1 - t0) * 1e3 / steps
+    phase = {}
+    for name, (launches, total) in prof.items():
+        phase[name] = {"launches": launches, "avg_ms": total / max(launches, 1), "ms_per_step": total / steps}
+    t_enum = sum(v["ms_per_step"] for k, v in phase.items()
+                 if k in ("k_part_count", "k_part_scan", "k_part_scatter", "k_bucket", "k_big"))
+    missing = missing_edge_ratio(msm, ctx, w, Xd, pairs[:mH], verified[:mE], sub=judge_sub)
+    res = {"ms_per_step": ms_step, "points_per_s": n / (ms_step / 1e3), "combinations": C,
+           "hamming_pairs": int(mH), "eps_pairs": int(mE), "phase": phase,
+           "hamming_pairs_per_s_enumerate": (mH / (t_enum / 1e3)) if t_enum else None,
+           "eps_pairs_per_s_total": mE / (ms_step / 1e3), "missing_edge_ratio": missing}
+    del pairs, verified, S
+    return res
+
+
+def roofline_of(res, w, n, W):
+    """Roofline object of the kernel with the most time per step."""
+    phase = res["phase"]
+    dom = max(phase, key=lambda k: phase[k]["ms_per_step"])
+    alg = algorithmic(dom, w, n, res["combinations"], res["hamming_pairs"], res["eps_pairs"], W)
+    if alg is None:
+        return {"kernel": dom, "bound": None, "achieved": None, "peak": None, "unit": None, "frac": None,
+                "traffic": None}
+    amount, unit, bound = alg
+    achieved = amount / (phase[dom]["avg_ms"] / 1e3)
+    peak = {"mfma": FP32_MFMA_PEAK_TFLOPS, "mfma_bf16": BF16_MFMA_PEAK_TFLOPS}.get(bound, HBM_PEAK_GBS)
+    return {"kernel": dom, "bound": "mfma" if bound.startswith("mfma") else bound, "achieved": round(achieved, 2),
+            "peak": peak, "unit": unit, "frac": round(achieved / peak, 4), "traffic": None}
+
+
+def compact(res):
+    out = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in res.items() if k != "phase"}
+    out["kernels"] = {k: {kk: round(vv, 4) if isinstance(vv, float) else vv for kk, vv in v.items()}
+                      for k, v in sorted(res["phase"].items())}
+    return out
+
+
+def run_learned(args):
+    """The learned-projection form: 2M mixture points (cluster radius reading
+    of sigma), a 128-512-128 network trained on the GPU on epsilon-pairs and
+    non-pairs mined by the exhaustive judge from a 100k-point sample, then
+    whole steps with learned and with random strings at equal ell, each
+    judged on a 50k subsample disjoint from the training sample."""
+    import numpy as np
+    import torch
+
+    from paper_0904_3151_amd import inputs as I
+    from paper_0904_3151_amd import learned as L
+    from paper_0904_3151_amd import msm
+
+    w = I.LEARNED_SCALE
+    log(f"generating {w.name} (radius)")
+    X, R = I.workload_inputs(w, sigma_mode="radius")
+    n, W = w.n, (w.ell + 63) // 64
+    dev = torch.device("cuda:0")
+    Xd = torch.from_numpy(X).to(dev)
+    Rd = torch.from_numpy(R).to(dev)
+    ctx = msm.Context(0)
+    train_idx = I.subsample_indices(n, 100_000, w.seed_sub + 7)
+    held = np.setdiff1d(np.arange(n, dtype=np.int64), train_idx)
+    judge_sub = torch.from_numpy(held[I.subsample_indices(held.size, w.subsample, w.seed_sub)]).to(dev)
+    Xt = Xd[torch.from_numpy(train_idx).to(dev)].contiguous()
+    t0 = time.perf_counter()
+    tp, tl, stats = L.mine_pairs(ctx, Xt, w.eps, n_pos=200_000, n_neg=200_000, seed=w.seed_sub + 8)
+    torch.cuda.synchronize()
+    t_mine = time.perf_counter() - t0
+    cfg = L.TrainConfig(hid=512, ell=w.ell, h=w.h, lam=0.05, lr=1e-3, batch=4096, epochs=args.epochs, seed=11)
+    t0 = time.perf_counter()
+    params, _, _, losses, nsteps = L.train(ctx, Xt, tp, tl, cfg, I.mlp_initial_parameters(w.d, cfg.hid, w.ell, 12))
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    log(f"mined {stats} in {t_mine:.1f} s; trained {nsteps - 1} steps in {t_train:.1f} s, "
+        f"loss {losses[0]:.3f} -> {np.mean(losses[-20:]):.3f}")
+
+    learned = run_mixture(msm, ctx, w, X, Xd, lambda S: msm.msm_project_mlp(ctx, Xd, params, cfg.hid, w.ell, S),
+                          args.steps, args.warmup, judge_sub)
+    log(f"learned: {compact(learned)}")
+    rand = run_mixture(msm, ctx, w, X, Xd, lambda S: msm.msm_project(ctx, Xd, Rd, S), args.steps, args.warmup,
+                       judge_sub)
+    log(f"random: {compact(rand)}")
+    flops = 2.0 * n * (w.d * cfg.hid + cfg.hid * w.ell)
+    ph = learned["phase"].get("k_mlp_fused")
+    mlp_roof = None
+    if ph:
+        ach = flops / (ph["avg_ms"] / 1e3) / 1e12
+        mlp_roof = {"kernel": "k_mlp_fused", "bound": "mfma", "achieved": round(ach, 2),
+                    "peak": BF16_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(ach / BF16_MFMA_PEAK_TFLOPS, 4),
+                    "traffic": None}
+    out = {"metric": METRIC, "value": round(learned["points_per_s"], 1), "unit": "points/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(learned["ms_per_step"], 4),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
+           "data": "synthetic Gaussian mixture, sigma_mode=radius",
+           "config": {"workload": w.name, "n": n, "d": w.d, "ell": w.ell, "k": w.k, "h": w.h, "eps": w.eps,
+                      "metric": w.metric, "hidden": cfg.hid, "train_sample": int(train_idx.size),
+                      "judge_subsample": int(judge_sub.numel())},
+           "training": {"mining": stats, "mining_s": round(t_mine, 2), "steps": nsteps - 1,
+                        "train_s": round(t_train, 2), "loss_first": losses[0],
+                        "loss_last20": float(np.mean(losses[-20:])), "config": vars(cfg)},
+           "learned": compact(learned), "random_lsh": compact(rand),
+           "roofline": roofline_of(learned, w, n, W), "roofline_projection": mlp_roof, "cpu_baseline": None}
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -205,8 +360,12 @@ def main():
     ap.add_argument("--sigma-mode", default="coord", choices=["coord", "radius"])
     ap.add_argument("--cpu-sample", type=int, default=0, help="rows for the CPU oracle (0: all)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="paper", choices=["paper", "precision"],
-                    help="paper: the 1M mixture (default); precision: 4M sparse rows, FP32/BF16/FP8")
+    ap.add_argument("--no-second-reading", action="store_true",
+                    help="skip the run under the other reading of sigma")
+    ap.add_argument("--epochs", type=int, default=10, help="training epochs of the learned form")
+    ap.add_argument("--workload", default="paper", choices=["paper", "precision", "learned"],
+                    help="paper: the 1M mixture (default); precision: 4M sparse rows, FP32/BF16/FP8; "
+                         "learned: 2M mixture, trained network vs random projection")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -216,8 +375,10 @@ def main():
     if args.workload == "precision":
         run_precision(args)
         return
+    if args.workload == "learned":
+        run_learned(args)
+        return
 
-    import numpy as np
     import torch
 
     from paper_0904_3151_amd import inputs as I
@@ -230,58 +391,23 @@ def main():
     dev = torch.device("cuda:0")
     Xd = torch.from_numpy(X).to(dev)
     Rd = torch.from_numpy(R).to(dev)
-    S = torch.empty((n, W), dtype=torch.int64, device=dev)
     ctx = msm.Context(0)
-    C = 1
-    for t in range(w.h):
-        C = C * (w.k - t) // (t + 1)
-
-    # size the output buffers with a count-only pass
-    msm.msm_project(ctx, Xd, Rd, S)
-    _, mH = msm.msm_enumerate_pairs(ctx, S, w.ell, w.k, w.h, cap=0)
-    pairs = torch.empty((max(1, int(mH * 1.05) + 1024), 2), dtype=torch.int32, device=dev)
-    verified = torch.empty_like(pairs)
-    log(f"hamming pairs {mH}")
-
-    def step():
-        msm.msm_project(ctx, Xd, Rd, S)
-        P, m = msm.msm_enumerate_pairs(ctx, S, w.ell, w.k, w.h, pairs=pairs)
-        V, kept = msm.msm_verify(ctx, Xd, P, w.metric, w.eps, out=verified)
-        return m, kept
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-
-    msm.msm_profile_reset(ctx)
-    msm.msm_profile_enable(ctx, True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        mH, mE = step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    msm.msm_profile_enable(ctx, False)
-    prof = msm.msm_profile_read(ctx)
-
-    ms_step = (t1 - t0) * 1e3 / args.steps
-    phase = {}
-    for name, (launches, total) in prof.items():
-        phase[name] = {"launches": launches, "avg_ms": total / max(launches, 1),
-                       "ms_per_step": total / args.steps}
-    t_enum = sum(v["ms_per_step"] for k, v in phase.items()
-                 if k in ("k_part_count", "k_part_scan", "k_part_scatter", "k_bucket", "k_big"))
-    dom = max(phase, key=lambda k: phase[k]["ms_per_step"])
-    roof = None
-    alg = algorithmic(dom, w, n, C, mH, mE, W)
-    if alg is not None:
-        amount, unit, bound = alg
-        achieved = amount / (phase[dom]["avg_ms"] / 1e3)
-        peak = FP32_MFMA_PEAK_TFLOPS if bound == "mfma" else HBM_PEAK_GBS
-        roof = {"kernel": dom, "bound": bound, "achieved": round(achieved, 2), "peak": peak, "unit": unit,
-                "frac": round(achieved / peak, 4), "traffic": None}
-
-    missing = missing_edge_ratio(msm, ctx, w, Xd, pairs[:mH], verified[:mE])
+    res = run_mixture(msm, ctx, w, X, Xd, lambda S: msm.msm_project(ctx, Xd, Rd, S), args.steps, args.warmup)
+    roof = roofline_of(res, w, n, W)
+    second = None
+    if not args.no_second_reading:
+        other = "radius" if args.sigma_mode == "coord" else "coord"
+        log(f"generating {w.name} ({other})")
+        X2, _ = I.workload_inputs(w, sigma_mode=other)
+        X2d = torch.from_numpy(X2).to(dev)
+        del X2
+        r2 = run_mixture(msm, ctx, w, None, X2d, lambda S: msm.msm_project(ctx, X2d, Rd, S), args.steps,
+                         args.warmup)
+        second = compact(r2)
+        second["sigma_mode"] = other
+        second["roofline"] = roofline_of(r2, w, n, W)
+        del X2d
+        torch.cuda.empty_cache()
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -289,28 +415,29 @@ def main():
         log(f"cpu baseline on {sample} points")
         cpu = cpu_baseline(w, X, R, sample)
 
+    c = compact(res)
     out = {
         "metric": METRIC,
-        "value": round(n / (ms_step / 1e3), 1),
+        "value": round(res["points_per_s"], 1),
         "unit": "points/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 4),
+        "ms_per_step": round(res["ms_per_step"], 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": f"synthetic Gaussian mixture, sigma_mode={args.sigma_mode}",
         "config": {"workload": w.name, "n": n, "d": w.d, "ell": w.ell, "k": w.k, "h": w.h, "eps": w.eps,
-                   "metric": w.metric, "combinations": C, "sigma_mode": args.sigma_mode},
-        "edges_per_s": {"hamming_pairs_per_s_enumerate": round(mH / (t_enum / 1e3), 1) if t_enum else None,
-                        "eps_pairs_per_s_total": round(mE / (ms_step / 1e3), 1)},
-        "counts": {"hamming_pairs": int(mH), "eps_pairs": int(mE)},
-        "kernels": {k: {kk: round(vv, 4) if isinstance(vv, float) else vv for kk, vv in v.items()}
-                    for k, v in sorted(phase.items())},
-        "missing_edge_ratio": missing,
+                   "metric": w.metric, "combinations": res["combinations"], "sigma_mode": args.sigma_mode},
+        "edges_per_s": {"hamming_pairs_per_s_enumerate": c["hamming_pairs_per_s_enumerate"],
+                        "eps_pairs_per_s_total": c["eps_pairs_per_s_total"]},
+        "counts": {"hamming_pairs": res["hamming_pairs"], "eps_pairs": res["eps_pairs"]},
+        "kernels": c["kernels"],
+        "missing_edge_ratio": res["missing_edge_ratio"],
         "roofline": roof,
+        "second_reading": second,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
