@@ -246,6 +246,72 @@ msm_status msm_mlp_train(msm_ctx* ctx, const float* X, int64_t n, int32_t d, int
                          int64_t steps, int64_t first_step, float lr, float h, float lam,
                          float* losses, void* stream);
 
+/* Batched form: many independent instances of the whole path, each its own
+ * problem of Definition 1.1's Hamming stage: strings by eq. (3) from its
+ * own X and R, then all its pairs within Hamming distance h (Sections
+ * 2.1-2.2), written with indices local to the instance. All instances share
+ * ell, k and h. */
+typedef struct {
+    const float* X;  /* DEVICE float[n rows, ldx stride] */
+    const float* R;  /* DEVICE float[d * ell], row-major */
+    uint64_t* S;     /* DEVICE uint64[n * W], written by every run */
+    uint32_t* pairs; /* DEVICE uint32[2 * cap], 8-byte aligned; NULL with cap == 0 */
+    int64_t n;       /* points, >= 0 */
+    int64_t ldx;     /* >= d */
+    int64_t cap;     /* pairs that fit */
+    int32_t d;       /* >= 1 when n > 0 */
+    int32_t reserved;
+} msm_instance;
+
+/* A tuning parameter set of the batched enumeration and its measured time. */
+typedef struct {
+    int32_t bucket_target;     /* points per partition bucket aimed at */
+    int32_t digit_bits;        /* width of the radix digit counted inside a bucket */
+    int32_t buckets_per_group; /* buckets taken by one workgroup */
+    float ms;                  /* enumeration time of the whole batch, -1 if untimed */
+} msm_batch_config;
+
+typedef struct msm_batch msm_batch;
+
+/* Plan a batch: checks the instances, allocates the plan's device memory
+ * (about 8 * N * min(C(k,h), groups) bytes of partition plus the
+ * concatenated strings, N = total points) and uploads its tables. With
+ * autotune != 0 every candidate configuration (bucket target 256, 512 or
+ * 1024 points, digit 8, 10 or 12 bits, 2 or 8 buckets per workgroup) is
+ * timed on this batch and the fastest kept; this runs the batch, so S and
+ * pairs of the instances are written. The descriptors are copied: the
+ * buffers they point to must stay valid for the plan's life.
+ *   inst   HOST msm_instance[count], 1 <= count <= 65535
+ *   out    HOST, receives the plan
+ * Limits as msm_enumerate_pairs; total points below 2^32.
+ * Errors: MSM_E_INVALID (arguments), MSM_E_UNSUPPORTED (k, C(k,h)),
+ * MSM_E_NOMEM, MSM_E_HIP. Synchronises `stream`. */
+msm_status msm_batch_create(msm_ctx* ctx, const msm_instance* inst, int32_t count, int32_t ell,
+                            int32_t k, int32_t h, int32_t autotune, msm_batch** out, void* stream);
+
+/* Enqueue one run of the batch on `stream`: projection of every instance,
+ * then its Hamming pairs. Only kernel launches are enqueued (counters are
+ * cleared by kernels, nothing is copied, nothing waits on the host), so the
+ * call may be captured into a HIP graph.
+ *   m_dev  DEVICE int64[count]: pairs of each instance. When m_dev[i] >
+ *          cap_i the instance's list holds an unspecified cap_i of them.
+ * Runs of one plan must not overlap: they share its device memory.
+ * Errors: MSM_E_INVALID (NULL plan, NULL or unaligned m_dev). */
+msm_status msm_batch_run(msm_batch* b, int64_t* m_dev, void* stream);
+
+/* msm_batch_run captured once into a HIP graph (on the plan's own stream;
+ * again whenever m_dev changes) and launched on `stream` as one graph. */
+msm_status msm_batch_launch_graph(msm_batch* b, int64_t* m_dev, void* stream);
+
+/* The configuration in use and, when the plan was tuned, every candidate
+ * with its time (up to cap HOST records; *n_tried gets their number). */
+msm_status msm_batch_tuning(const msm_batch* b, msm_batch_config* chosen, msm_batch_config* tried,
+                            int32_t cap, int32_t* n_tried);
+
+/* Release a plan and its device memory; no run of it may be in flight.
+ * NULL is ignored. */
+void msm_batch_destroy(msm_batch* b);
+
 /* Per-kernel timing. While enabled, every kernel launch of the context is
  * bracketed by two HIP events on its stream (a few microseconds of overhead
  * per launch). Timings accumulate per kernel name until msm_profile_reset. */

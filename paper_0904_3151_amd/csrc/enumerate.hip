@@ -1,789 +1,18 @@
-// Multiple sorting method with blockwise masking (Sections 2.1-2.2) on gfx950.
-//
-// For every set B of h masked blocks the points must be grouped by their
-// B-masked string s^B, and pairs inside a group tested. Only grouping is
-// needed, not a full order (the paper's own radix-sort trick makes the same
-// observation), so the sort key is a 32-bit mix of the masked string rather
-// than the string itself:
-//
-//   1. partition  one MSD radix pass over HBM on the top r1 bits of the mix:
-//                 LDS histograms per tile (k_part_count), a column scan of
-//                 the (tile, bucket) counts (k_part_scan), and a scatter of
-//                 (mix << 32 | index) into bucket order (k_part_scatter).
-//   2. bucket     a workgroup takes a few buckets (about 512 points each):
-//                 the next 11 bits of the mix are counted in an LDS
-//                 histogram (the second radix digit), whose bins with two or
-//                 more members are the runs; a wavefront prefix scan places
-//                 the run members in LDS and a flat, balanced loop tests all
-//                 pairs inside runs (k_bucket).
-//   3. overflow   buckets larger than the LDS capacity are tested tile by
-//                 tile straight from HBM (k_big).
-//
-// Equal masked strings always share a mix, so no pair is lost. Different
-// strings can share a mix; that only adds candidates, because the pair test
-// below is exact:
-//
-//   x = s_i xor s_j;  keep iff popcount(x) <= h            (Hamming filter)
-//                     and x has no bit outside the blocks of B  (s_i^B == s_j^B)
-//                     and B is the canonical set for the blocks where x != 0.
-//
-// Canonical set: a pair whose differing blocks form D (|D| <= h) falls into
-// one group under every h-set B containing D. It is written only under
-// D plus the smallest blocks not in D, i.e. iff D is a subset of B and every
-// block of B above the smallest unmasked block is in D. So each pair comes
-// out exactly once without any exchange between combinations.
-#include "msm_internal.h"
-
-#include <algorithm>
-#include <vector>
+// Multiple sorting method with blockwise masking (Sections 2.1-2.2) on gfx950:
+// host driver of msm_enumerate_pairs and msm_enumerate_replicates. The
+// method and its kernels are described in msm_enum.h.
+#include "msm_enum.h"
 
 namespace {
-
-constexpr int MAXW = 4;
-constexpr int MAXK = 64;
-constexpr int PART_THREADS = 256;
-constexpr int SCAN_THREADS = 1024;
-constexpr int BK_THREADS = 256;
-constexpr int BK_WAVES = BK_THREADS / 64;
-constexpr int BK_MAXB = 4;                        // 64-element batches per wave
-constexpr int BK_CAP = BK_WAVES * 64 * BK_MAXB;   // largest bucket sorted in LDS
-constexpr int BK_PAIR_CHUNK = 8;                  // consecutive pairs per lane
-constexpr int BK_GROUP = 8;                       // buckets per workgroup
-constexpr int BK_OUT = 512;                       // staged output pairs per workgroup
-constexpr int BK_DIGIT = 10;                      // mix bits counted inside a bucket
-constexpr int BK_BINS = 1 << BK_DIGIT;
-constexpr int BIG_TILE = 256;
-constexpr int MAX_BUCKETS = 8192;
-constexpr int TARGET_BUCKET = 512;
-
-constexpr int MAXHI = 4;   // blocks of `hi` tested from unrolled masks
-
-struct Combo {                    // one set B of masked blocks
-    uint64_t keep[MAXW];          // characters below ell outside the blocks of B
-    uint64_t hi;                  // blocks of B above the smallest block not in B
-    int32_t nhi;                  // number of blocks in hi
-    int32_t pad0;
-    uint64_t pad1[2];
-    uint64_t himask[MAXHI][MAXW]; // character masks of the first MAXHI blocks of hi
-};
-static_assert(sizeof(Combo) == 192, "Combo layout");
-
-struct Ovf {
-    uint32_t c, beg, m, pad;
-};
-
-struct Params {
-    const uint64_t* S;       // strings of the replicate being enumerated
-    const uint64_t* Sall;    // all replicates, replicate-major
-    uint64_t rep_stride;     // words between replicates (n * W)
-    int rep;                 // index of the replicate being enumerated
-    int64_t n;
-    const Combo* combos;     // combinations of this launch group
-    const uint64_t* bm;      // [k][MAXW] block masks
-    int k, h;
-    uint64_t valid[MAXW];    // bits below ell
-    int r1;                  // bucket bits (top bits of the mix)
-    int nb;                  // 1 << r1
-    int sort_lo;             // runs share mix >> sort_lo
-    int T, nt;               // partition tile size and count
-    int units;               // combinations of the group x tiles
-    uint32_t* counts;        // [c][t][b] tile counts, then tile offsets
-    uint32_t* base;          // [c][nb + 1] bucket starts
-    uint64_t* part;          // [c][n] (mix << 32 | index) in bucket order
-    uint32_t* pairs;
-    unsigned long long cap;
-    unsigned long long* counter;
-    Ovf* ovf;
-    uint32_t* ovf_count;
-};
-
-__device__ __forceinline__ uint64_t mix64(uint64_t z)
-{
-    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
-    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
-    return z ^ (z >> 31);
-}
-
-template <int W>
-__device__ __forceinline__ uint32_t masked_mix(const uint64_t (&s)[W], const uint64_t (&keep)[W])
-{
-    uint64_t z = 0x9e3779b97f4a7c15ull;
-#pragma unroll
-    for (int w = 0; w < W; ++w) z = mix64(z ^ (s[w] & keep[w]));
-    return (uint32_t)(z >> 32);
-}
-
-template <int W>
-__device__ __forceinline__ void load_string(const uint64_t* __restrict__ S, uint64_t i, uint64_t (&s)[W])
-{
-    const uint64_t* p = S + i * W;
-#pragma unroll
-    for (int w = 0; w < W; ++w) s[w] = p[w];
-}
-
-template <int W>
-__device__ __forceinline__ void load_keep(const Combo* cb, uint64_t (&keep)[W])
-{
-#pragma unroll
-    for (int w = 0; w < W; ++w) keep[w] = cb->keep[w];
-}
-
-// -------------------------------------------------------------------------
-// 1. partition
-//
-// Workgroups are dispatched round-robin over the 8 XCDs, each with its own
-// L2. The (combination, tile) units are cut into 8 contiguous ranges in
-// combination-major order and XCD x runs range x, so all tiles of a
-// combination scatter through one L2, where the partial lines that
-// neighbouring tiles write into the same bucket can merge.
-constexpr int NUM_XCD = 8;
-
-__device__ __forceinline__ bool xcd_unit(int units, int& cl, int& t, int nt)
-{
-    const int per = (units + NUM_XCD - 1) / NUM_XCD;
-    const int u = (int)(blockIdx.x % NUM_XCD) * per + (int)(blockIdx.x / NUM_XCD);
-    if (u >= units) return false;
-    cl = u / nt;
-    t = u % nt;
-    return true;
-}
-
-template <int W>
-__global__ __launch_bounds__(PART_THREADS) void k_part_count(Params p)
-{
-    extern __shared__ uint32_t hist[];
-    int cl, t;
-    if (!xcd_unit(p.units, cl, t, p.nt)) return;
-    uint64_t keep[W];
-    load_keep<W>(p.combos + cl, keep);
-    for (int b = threadIdx.x; b < p.nb; b += PART_THREADS) hist[b] = 0;
-    __syncthreads();
-    const int64_t beg = (int64_t)t * p.T;
-    const int64_t end = min(p.n, beg + p.T);
-    for (int64_t i = beg + threadIdx.x; i < end; i += PART_THREADS) {
-        uint64_t s[W];
-        load_string<W>(p.S, (uint64_t)i, s);
-        const uint32_t mx = masked_mix<W>(s, keep);
-        const uint32_t b = p.r1 ? (mx >> (32 - p.r1)) : 0u;
-        atomicAdd(&hist[b], 1u);
-    }
-    __syncthreads();
-    uint32_t* out = p.counts + ((size_t)cl * p.nt + t) * p.nb;
-    for (int b = threadIdx.x; b < p.nb; b += PART_THREADS) out[b] = hist[b];
-}
-
-// Per combination: counts[t][b] -> offset of tile t inside bucket b, and
-// base[b] = start of bucket b.
-__global__ __launch_bounds__(SCAN_THREADS) void k_part_scan(Params p)
-{
-    extern __shared__ uint32_t tot[];  // nb totals, then one word per wave
-    const int cl = blockIdx.x;
-    uint32_t* cnt = p.counts + (size_t)cl * p.nt * p.nb;
-    for (int b = threadIdx.x; b < p.nb; b += SCAN_THREADS) {
-        uint32_t run = 0;
-        int t = 0;
-        for (; t + 8 <= p.nt; t += 8) {
-            uint32_t v[8];
-#pragma unroll
-            for (int q = 0; q < 8; ++q) v[q] = cnt[(size_t)(t + q) * p.nb + b];
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                cnt[(size_t)(t + q) * p.nb + b] = run;
-                run += v[q];
-            }
-        }
-        for (; t < p.nt; ++t) {
-            const uint32_t v = cnt[(size_t)t * p.nb + b];
-            cnt[(size_t)t * p.nb + b] = run;
-            run += v;
-        }
-        tot[b] = run;
-    }
-    __syncthreads();
-    uint32_t* wsum = tot + p.nb;
-    const int per = (p.nb + SCAN_THREADS - 1) / SCAN_THREADS;
-    const int b0 = threadIdx.x * per;
-    const int b1 = min(p.nb, b0 + per);
-    uint32_t s = 0;
-    for (int b = b0; b < b1; ++b) s += tot[b];
-    const uint32_t incl = msm::wave_incl_scan(s);
-    const int wave = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 63) wsum[wave] = incl;
-    __syncthreads();
-    uint32_t pre = 0;
-    for (int w = 0; w < wave; ++w) pre += wsum[w];
-    uint32_t run = pre + incl - s;
-    uint32_t* base = p.base + (size_t)cl * (p.nb + 1);
-    for (int b = b0; b < b1; ++b) {
-        const uint32_t v = tot[b];
-        base[b] = run;
-        run += v;
-    }
-    if (threadIdx.x == 0) base[p.nb] = (uint32_t)p.n;
-}
-
-template <int W>
-__global__ __launch_bounds__(PART_THREADS) void k_part_scatter(Params p)
-{
-    extern __shared__ uint32_t cursor[];
-    int cl, t;
-    if (!xcd_unit(p.units, cl, t, p.nt)) return;
-    uint64_t keep[W];
-    load_keep<W>(p.combos + cl, keep);
-    const uint32_t* off = p.counts + ((size_t)cl * p.nt + t) * p.nb;
-    const uint32_t* base = p.base + (size_t)cl * (p.nb + 1);
-    for (int b = threadIdx.x; b < p.nb; b += PART_THREADS) cursor[b] = base[b] + off[b];
-    __syncthreads();
-    uint64_t* part = p.part + (size_t)cl * p.n;
-    const int64_t beg = (int64_t)t * p.T;
-    const int64_t end = min(p.n, beg + p.T);
-    for (int64_t i = beg + threadIdx.x; i < end; i += PART_THREADS) {
-        uint64_t s[W];
-        load_string<W>(p.S, (uint64_t)i, s);
-        const uint32_t mx = masked_mix<W>(s, keep);
-        const uint32_t b = p.r1 ? (mx >> (32 - p.r1)) : 0u;
-        const uint32_t pos = atomicAdd(&cursor[b], 1u);
-        part[pos] = ((uint64_t)mx << 32) | (uint64_t)(uint32_t)i;
-    }
-}
-
-// -------------------------------------------------------------------------
-// Exact pair test of one candidate (see the file comment).
-
-template <int W>
-__device__ __forceinline__ bool pair_ok(const uint64_t* a, const uint64_t* b, const Params& p,
-                                        const uint64_t (&keep)[W], uint64_t hi,
-                                        const uint64_t* __restrict__ bmL)
-{
-    uint64_t x[W];
-    int ham = 0;
-    uint64_t outside = 0;
-#pragma unroll
-    for (int w = 0; w < W; ++w) {
-        x[w] = (a[w] ^ b[w]) & p.valid[w];
-        ham += __popcll(x[w]);
-        outside |= x[w] & keep[w];
-    }
-    bool ok = (ham <= p.h) && (outside == 0);
-    uint64_t need = hi;
-    while (ok && need) {
-        const int blk = __builtin_ctzll(need);
-        need &= need - 1;
-        uint64_t any = 0;
-#pragma unroll
-        for (int w = 0; w < W; ++w) any |= x[w] & bmL[blk * W + w];
-        ok = any != 0;
-    }
-    return ok;
-}
-
-// The same test, branch-free, with the masks of the first MAXHI blocks of
-// `hi` held in registers (hm). Combinations with more blocks in `hi` finish
-// with a loop over the block masks in LDS.
-template <int W>
-__device__ __forceinline__ bool pair_ok_fast(const uint64_t* a, const uint64_t* b, const Params& p,
-                                             const uint64_t (&keep)[W], const uint64_t (&hm)[MAXHI][W], int nhi,
-                                             uint64_t hi_rest, const uint64_t* __restrict__ bmL)
-{
-    uint64_t x[W];
-    int ham = 0;
-    uint64_t outside = 0;
-#pragma unroll
-    for (int w = 0; w < W; ++w) {
-        x[w] = (a[w] ^ b[w]) & p.valid[w];
-        ham += __popcll(x[w]);
-        outside |= x[w] & keep[w];
-    }
-    bool ok = (ham <= p.h) & (outside == 0);
-#pragma unroll
-    for (int s = 0; s < MAXHI; ++s) {
-        uint64_t any = 0;
-#pragma unroll
-        for (int w = 0; w < W; ++w) any |= x[w] & hm[s][w];
-        ok &= (s >= nhi) | (any != 0);
-    }
-    if (hi_rest) {
-        uint64_t need = hi_rest;
-        while (need) {
-            const int blk = __builtin_ctzll(need);
-            need &= need - 1;
-            uint64_t any = 0;
-#pragma unroll
-            for (int w = 0; w < W; ++w) any |= x[w] & bmL[blk * W + w];
-            ok &= any != 0;
-        }
-    }
-    return ok;
-}
-
-// Cross-replicate dedup: a pair found in replicate q is written only if its
-// Hamming distance exceeds h in every earlier replicate g < q.
-template <int W>
-__device__ __forceinline__ bool far_in_earlier(const Params& p, uint32_t i, uint32_t j)
-{
-    for (int g = 0; g < p.rep; ++g) {
-        const uint64_t* a = p.Sall + (uint64_t)g * p.rep_stride + (uint64_t)i * W;
-        const uint64_t* b = p.Sall + (uint64_t)g * p.rep_stride + (uint64_t)j * W;
-        int ham = 0;
-#pragma unroll
-        for (int w = 0; w < W; ++w) ham += __popcll((a[w] ^ b[w]) & p.valid[w]);
-        if (ham <= p.h) return false;
-    }
-    return true;
-}
-
-// -------------------------------------------------------------------------
-// 2. buckets, BK_GROUP consecutive ones per workgroup
-//
-// Inside a bucket one more radix digit (BK_DIGIT bits of the mix, below the
-// bucket bits) is counted in an LDS histogram; the count returned by each
-// element's atomic is its rank in its bin. The histogram is the run
-// segmentation: a bin with c >= 2 members is a run (equal masked strings
-// always share a bin) with c (c - 1) / 2 candidate pairs; singleton bins are
-// dropped. The first member of each run claims the run's index and its place
-// in a compact LDS array of run members with one packed 64-bit LDS atomic,
-// so no scan over the bins is needed. Members are scattered there with their
-// strings; each run then either claims a range of the flat pair index space
-// the same way or is dropped when it cannot hold a pair to write (below),
-// and a flat loop over the claimed pairs tests them. Bins that mix several
-// masked strings only add candidates, which the exact test rejects.
-
-template <int W>
-__global__ __launch_bounds__(BK_THREADS) void k_bucket(Params p)
-{
-    __shared__ uint32_t hist[BK_BINS];
-    __shared__ uint16_t binStart[BK_BINS];
-    __shared__ uint16_t binRun[BK_BINS];
-    __shared__ uint64_t keysB[BK_CAP];
-    __shared__ uint64_t sl[BK_CAP * W];
-    __shared__ uint16_t runS[BK_CAP / 2];
-    __shared__ uint16_t runL[BK_CAP / 2];
-    __shared__ unsigned long long runVar[BK_CAP / 2 * W];  // bits that vary inside the run
-    __shared__ uint16_t liveS[BK_CAP / 2];
-    __shared__ uint16_t liveL[BK_CAP / 2];
-    __shared__ uint32_t liveP[BK_CAP / 2];
-    __shared__ uint64_t bmL[MAXK * W];
-    __shared__ unsigned long long claimRun;   // runs << 32 | members
-    __shared__ unsigned long long claimPair;  // live runs << 32 | pairs
-    __shared__ uint2 obuf[BK_OUT];
-    __shared__ uint32_t ocnt;
-    __shared__ unsigned long long ogb;
-
-    const int cl = blockIdx.y;
-    const Combo* cb = p.combos + cl;
-    uint64_t keep[W];
-    load_keep<W>(cb, keep);
-    const uint64_t hi = cb->hi;
-    const int nhi = cb->nhi;
-    uint64_t hm[MAXHI][W];
-#pragma unroll
-    for (int s2 = 0; s2 < MAXHI; ++s2)
-#pragma unroll
-        for (int w = 0; w < W; ++w) hm[s2][w] = cb->himask[s2][w];
-    // blocks of hi beyond the first MAXHI (tested from bmL)
-    uint64_t hi_rest = hi;
-    for (int s2 = 0; s2 < MAXHI && hi_rest; ++s2) hi_rest &= hi_rest - 1;
-    for (int e = threadIdx.x; e < p.k * W; e += BK_THREADS) bmL[e] = p.bm[(e / W) * MAXW + (e % W)];
-    for (int e = threadIdx.x; e < BK_BINS; e += BK_THREADS) hist[e] = 0;
-    if (threadIdx.x == 0) ocnt = 0;
-    msm::PairStager<BK_OUT> out{obuf, &ocnt, &ogb, p.pairs, p.cap, p.counter};
-    const uint32_t* base = p.base + (size_t)cl * (p.nb + 1);
-    const uint64_t* part = p.part + (size_t)cl * p.n;
-    const int bk0 = blockIdx.x * BK_GROUP;
-    const int bk1 = min(p.nb, bk0 + BK_GROUP);
-    const int dsh = 32 + p.sort_lo;
-
-    // keys of the current bucket, loaded one bucket ahead
-    uint64_t key[BK_MAXB];
-    uint32_t nbeg = base[bk0];
-    uint32_t ncnt = base[bk0 + 1] - nbeg;
-#pragma unroll
-    for (int b = 0; b < BK_MAXB; ++b) {
-        const int pos = threadIdx.x + b * BK_THREADS;
-        key[b] = (ncnt <= (uint32_t)BK_CAP && pos < (int)ncnt) ? part[nbeg + pos] : ~0ull;
-    }
-
-    for (int bk = bk0; bk < bk1; ++bk) {
-        const uint32_t beg = nbeg;
-        const uint32_t cnt = ncnt;
-        uint64_t cur[BK_MAXB];
-#pragma unroll
-        for (int b = 0; b < BK_MAXB; ++b) cur[b] = key[b];
-        if (bk + 1 < bk1) {
-            nbeg = base[bk + 1];
-            ncnt = base[bk + 2] - nbeg;
-#pragma unroll
-            for (int b = 0; b < BK_MAXB; ++b) {
-                const int pos = threadIdx.x + b * BK_THREADS;
-                key[b] = (ncnt <= (uint32_t)BK_CAP && pos < (int)ncnt) ? part[nbeg + pos] : ~0ull;
-            }
-        }
-        __syncthreads();  // LDS of the previous bucket is free, hist is zero
-        if (cnt < 2) continue;
-        if (cnt > (uint32_t)BK_CAP) {
-            if (threadIdx.x == 0) {
-                const uint32_t o = atomicAdd(p.ovf_count, 1u);
-                p.ovf[o] = Ovf{(uint32_t)cl, beg, cnt, 0u};
-            }
-            continue;
-        }
-        const int m = (int)cnt;
-        if (threadIdx.x == 0) {
-            claimRun = 0;
-            claimPair = 0;
-        }
-        // Strings of the bucket's points, requested now and used after the
-        // histogram and the run claims, which hide the load latency.
-        uint64_t sreg[BK_MAXB][W];
-#pragma unroll
-        for (int b = 0; b < BK_MAXB; ++b) {
-            const int pos = threadIdx.x + b * BK_THREADS;
-            const uint64_t idx = pos < m ? (uint32_t)cur[b] : 0u;
-#pragma unroll
-            for (int w = 0; w < W; ++w) sreg[b][w] = pos < m ? p.S[idx * W + w] : 0ull;
-        }
-
-        // histogram of the in-bucket digit; the returned count is the rank
-        uint32_t dig[BK_MAXB], rank[BK_MAXB];
-#pragma unroll
-        for (int b = 0; b < BK_MAXB; ++b) {
-            const int pos = threadIdx.x + b * BK_THREADS;
-            dig[b] = (uint32_t)(cur[b] >> dsh) & (BK_BINS - 1);
-            rank[b] = pos < m ? atomicAdd(&hist[dig[b]], 1u) : 0xFFFFFFFFu;
-        }
-        __syncthreads();
-
-        // the first member of each run claims the run and its member range
-        uint32_t c[BK_MAXB];
-#pragma unroll
-        for (int b = 0; b < BK_MAXB; ++b) {
-            c[b] = rank[b] != 0xFFFFFFFFu ? hist[dig[b]] : 0u;
-            if (rank[b] == 0 && c[b] >= 2) {
-                const unsigned long long old = atomicAdd(&claimRun, (1ull << 32) | (unsigned long long)c[b]);
-                const uint32_t r = (uint32_t)(old >> 32);
-                const uint32_t ms = (uint32_t)old;
-                binStart[dig[b]] = (uint16_t)ms;
-                binRun[dig[b]] = (uint16_t)r;
-                runS[r] = (uint16_t)ms;
-                runL[r] = (uint16_t)c[b];
-#pragma unroll
-                for (int w = 0; w < W; ++w) runVar[r * W + w] = 0ull;
-            }
-        }
-        __syncthreads();
-
-        // scatter run members and gather their strings
-#pragma unroll
-        for (int b = 0; b < BK_MAXB; ++b) {
-            if (c[b] >= 2) {
-                const uint32_t q = binStart[dig[b]] + rank[b];
-                keysB[q] = cur[b];
-#pragma unroll
-                for (int w = 0; w < W; ++w) sl[q * W + w] = sreg[b][w];
-            }
-        }
-        const uint32_t nruns = (uint32_t)(claimRun >> 32);
-        __syncthreads();
-        // Each member ORs its difference from the run's first member into
-        // the run's mask of varying bits; the histogram is cleared for the
-        // next bucket.
-#pragma unroll
-        for (int b = 0; b < BK_MAXB; ++b) {
-            if (rank[b] != 0xFFFFFFFFu) {
-                if (hi && c[b] >= 2 && rank[b] > 0) {
-                    const uint32_t first = binStart[dig[b]];
-                    const uint32_t q = first + rank[b];
-                    const uint32_t r = binRun[dig[b]];
-#pragma unroll
-                    for (int w = 0; w < W; ++w) {
-                        const uint64_t x = sl[q * W + w] ^ sl[first * W + w];
-                        if (x) atomicOr(&runVar[r * W + w], (unsigned long long)x);
-                    }
-                }
-                hist[dig[b]] = 0;
-            }
-        }
-        if (nruns == 0) continue;
-        if (hi) __syncthreads();
-
-        // Each run claims its pairs, unless it cannot hold a pair to write:
-        // a pair is written only if it differs in every block of `hi`, so a
-        // block of `hi` that is constant over the whole run rules it out.
-        for (uint32_t r = threadIdx.x; r < nruns; r += BK_THREADS) {
-            const int s0 = runS[r], L = runL[r];
-            bool live = true;
-            uint64_t need = hi;
-            while (live && need) {
-                const int blk = __builtin_ctzll(need);
-                need &= need - 1;
-                uint64_t any = 0;
-#pragma unroll
-                for (int w = 0; w < W; ++w) any |= runVar[r * W + w] & p.valid[w] & bmL[blk * W + w];
-                live = any != 0;
-            }
-            if (live) {
-                const unsigned long long old =
-                    atomicAdd(&claimPair, (1ull << 32) | (unsigned long long)(L * (L - 1) / 2));
-                const uint32_t q = (uint32_t)(old >> 32);
-                liveS[q] = (uint16_t)s0;
-                liveL[q] = (uint16_t)L;
-                liveP[q] = (uint32_t)old;
-            }
-        }
-        __syncthreads();
-        const uint32_t nlive = (uint32_t)(claimPair >> 32);
-        const uint32_t P = (uint32_t)claimPair;
-        if (P == 0) continue;
-
-        // Flat loop over all claimed pairs (a < b), row-major per run; each
-        // lane tests BK_PAIR_CHUNK consecutive pairs, keeps the results in a
-        // bit mask and appends the passing ones once per chunk.
-        for (uint32_t t0 = 0; t0 < P; t0 += BK_THREADS * BK_PAIR_CHUNK) {
-            const uint32_t t = t0 + threadIdx.x * BK_PAIR_CHUNK;
-            int r = 0, a = 0, bb = 1, L = 2, s0 = 0;
-            if (t < P) {
-                int lo = 0, hi2 = (int)nlive;
-                while (hi2 - lo > 1) {
-                    const int mid = (lo + hi2) >> 1;
-                    if (liveP[mid] <= t) lo = mid;
-                    else hi2 = mid;
-                }
-                r = lo;
-                L = liveL[r];
-                s0 = liveS[r];
-                const uint32_t u = t - liveP[r];
-                // row a of the upper triangle starts at f(a) = a (2L - a - 1) / 2;
-                // the float root is within one of the integer answer
-                const float q = (float)(2 * L - 1);
-                int aa = (int)((q - sqrtf(q * q - 8.0f * (float)u)) * 0.5f);
-                aa = max(0, min(aa, L - 2));
-                if (aa < L - 2 && (uint32_t)((aa + 1) * (2 * L - aa - 2) / 2) <= u) ++aa;
-                if (aa > 0 && (uint32_t)(aa * (2 * L - aa - 1) / 2) > u) --aa;
-                a = aa;
-                bb = a + 1 + (int)(u - (uint32_t)(a * (2 * L - a - 1) / 2));
-            }
-            // positions of the chunk's candidates first, then the tests
-            int pa[BK_PAIR_CHUNK], pb[BK_PAIR_CHUNK];
-#pragma unroll
-            for (int q = 0; q < BK_PAIR_CHUNK; ++q) {
-                pa[q] = min(s0 + a, BK_CAP - 1);
-                pb[q] = min(s0 + bb, BK_CAP - 1);
-                ++bb;
-                const bool wrapRow = bb == L;
-                a += wrapRow;
-                bb = wrapRow ? a + 1 : bb;
-                if (wrapRow && a >= L - 1) {
-                    ++r;
-                    a = 0;
-                    bb = 1;
-                    const int rr = min(r, (int)nlive - 1);
-                    L = liveL[rr];
-                    s0 = liveS[rr];
-                }
-            }
-            uint32_t okbits = 0;
-            uint32_t pi[BK_PAIR_CHUNK], pj[BK_PAIR_CHUNK];
-#pragma unroll
-            for (int q = 0; q < BK_PAIR_CHUNK; ++q) {
-                const bool live = t + q < P;
-                const uint64_t ka = keysB[pa[q]], kb = keysB[pb[q]];
-                pi[q] = (uint32_t)ka;
-                pj[q] = (uint32_t)kb;
-                const bool ok = live & ((ka >> 32) == (kb >> 32)) &
-                                pair_ok_fast<W>(&sl[pa[q] * W], &sl[pb[q] * W], p, keep, hm, nhi, hi_rest, bmL);
-                okbits |= (uint32_t)ok << q;
-            }
-            if (p.rep > 0 && okbits) {
-#pragma unroll
-                for (int q = 0; q < BK_PAIR_CHUNK; ++q)
-                    if (((okbits >> q) & 1u) && !far_in_earlier<W>(p, pi[q], pj[q])) okbits &= ~(1u << q);
-            }
-            // one append per lane per chunk: wave prefix of the counts, one
-            // LDS atomic per wave
-            const uint32_t nmine = (uint32_t)__popc(okbits);
-            const uint32_t incl = msm::wave_incl_scan(nmine);
-            const uint32_t wtot = __shfl(incl, 63, 64);
-            uint32_t wbase = 0;
-            if (wtot) {
-                if (__lane_id() == 0) wbase = atomicAdd(&ocnt, wtot);
-                wbase = __shfl(wbase, 0, 64);
-            }
-            uint32_t slot = wbase + incl - nmine;
-            // slots at or above BK_OUT do not fit in LDS: they go to the
-            // global list directly, reserved with one atomic per wave
-            const uint32_t first_out = max(wbase, (uint32_t)BK_OUT);
-            const uint32_t nover = (wtot && wbase + wtot > (uint32_t)BK_OUT) ? wbase + wtot - first_out : 0u;
-            unsigned long long gbase = 0;
-            if (nover) {
-                if (__lane_id() == 0) gbase = atomicAdd(p.counter, (unsigned long long)nover);
-                gbase = __shfl(gbase, 0, 64);
-            }
-#pragma unroll
-            for (int q = 0; q < BK_PAIR_CHUNK; ++q) {
-                if ((okbits >> q) & 1u) {
-                    const uint32_t lo2 = pi[q] < pj[q] ? pi[q] : pj[q];
-                    const uint32_t hi3 = pi[q] < pj[q] ? pj[q] : pi[q];
-                    if (slot < (uint32_t)BK_OUT) {
-                        obuf[slot] = make_uint2(lo2, hi3);
-                    } else {
-                        const unsigned long long g = gbase + (slot - first_out);
-                        if (g < p.cap) *reinterpret_cast<uint2*>(p.pairs + 2 * g) = make_uint2(lo2, hi3);
-                    }
-                    ++slot;
-                }
-            }
-            if (t0 + BK_THREADS * BK_PAIR_CHUNK < P) out.maybe_flush(BK_OUT / 2);
-        }
-        out.maybe_flush(BK_OUT / 2);
-    }
-    out.flush();
-}
-
-// -------------------------------------------------------------------------
-// 3. buckets above BK_CAP: all pairs, tile against tile, from HBM. A pair
-// is tested only when the full 32-bit mixes agree.
-
-template <int W>
-__global__ __launch_bounds__(BIG_TILE) void k_big(Params p, const Ovf* __restrict__ ovf,
-                                                 const uint64_t* __restrict__ tile0, int novf)
-{
-    __shared__ uint64_t kR[BIG_TILE], kC[BIG_TILE];
-    __shared__ uint64_t sR[BIG_TILE * W], sC[BIG_TILE * W];
-    __shared__ uint64_t bmL[MAXK * W];
-    __shared__ uint2 obuf[BK_OUT];
-    __shared__ uint32_t ocnt;
-    __shared__ unsigned long long ogb;
-    if (threadIdx.x == 0) ocnt = 0;
-    msm::PairStager<BK_OUT> out{obuf, &ocnt, &ogb, p.pairs, p.cap, p.counter};
-    const uint64_t tix = blockIdx.x;
-    int lo = 0, hi2 = novf;
-    while (hi2 - lo > 1) {
-        const int mid = (lo + hi2) >> 1;
-        if (tile0[mid] <= tix) lo = mid;
-        else hi2 = mid;
-    }
-    const Ovf e = ovf[lo];
-    const int64_t nT = (e.m + BIG_TILE - 1) / BIG_TILE;
-    const int64_t u = (int64_t)(tix - tile0[lo]);
-    // (ta, tb), ta <= tb, row-major over the upper triangle with diagonal
-    const double q = (double)(2 * nT + 1);
-    int64_t ta = (int64_t)((q - sqrt(q * q - 8.0 * (double)u)) * 0.5);
-    ta = max<int64_t>(0, min<int64_t>(ta, nT - 1));
-    while (ta < nT - 1 && (ta + 1) * (2 * nT - ta) / 2 <= u) ++ta;
-    while (ta > 0 && ta * (2 * nT - ta + 1) / 2 > u) --ta;
-    const int64_t tb = ta + (u - ta * (2 * nT - ta + 1) / 2);
-
-    const Combo* cb = p.combos + e.c;
-    uint64_t keep[W];
-    load_keep<W>(cb, keep);
-    const uint64_t hi = cb->hi;
-    for (int x = threadIdx.x; x < p.k * W; x += BIG_TILE) bmL[x] = p.bm[(x / W) * MAXW + (x % W)];
-    const uint64_t* part = p.part + (size_t)e.c * p.n + e.beg;
-    const int64_t ra = ta * BIG_TILE + threadIdx.x;
-    const int64_t ca = tb * BIG_TILE + threadIdx.x;
-    const bool rv = ra < (int64_t)e.m;
-    const bool cv = ca < (int64_t)e.m;
-    kR[threadIdx.x] = rv ? part[ra] : 0ull;
-    kC[threadIdx.x] = cv ? part[ca] : 0ull;
-#pragma unroll
-    for (int w = 0; w < W; ++w) {
-        sR[threadIdx.x * W + w] = rv ? p.S[(uint64_t)(uint32_t)kR[threadIdx.x] * W + w] : 0ull;
-        sC[threadIdx.x * W + w] = cv ? p.S[(uint64_t)(uint32_t)kC[threadIdx.x] * W + w] : 0ull;
-    }
-    __syncthreads();
-    const int ncol = (int)min<int64_t>(BIG_TILE, (int64_t)e.m - tb * BIG_TILE);
-    const uint32_t mine = (uint32_t)(kR[threadIdx.x] >> 32);
-    const bool diag = ta == tb;
-    const uint32_t ii = (uint32_t)kR[threadIdx.x];
-    for (int jj = 0; jj < ncol; ++jj) {
-        const uint64_t kc = kC[jj];
-        bool ok = rv && (!diag || jj > (int)threadIdx.x) && (uint32_t)(kc >> 32) == mine;
-        if (ok) ok = pair_ok<W>(&sR[threadIdx.x * W], &sC[jj * W], p, keep, hi, bmL);
-        const uint32_t jv = (uint32_t)kc;
-        if (ok && p.rep > 0) ok = far_in_earlier<W>(p, ii, jv);
-        out.push(ok, ii < jv ? ii : jv, ii < jv ? jv : ii);
-        if ((jj & 7) == 7) out.maybe_flush(BK_OUT / 2);
-    }
-    out.flush();
-}
-
-__global__ void k_zero_u64(unsigned long long* a, int n)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) a[i] = 0ull;
-}
-
-__global__ void k_zero_u32(uint32_t* a, int n)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) a[i] = 0u;
-}
-
-int64_t binom(int a, int b)
-{
-    if (b < 0 || b > a) return 0;
-    int64_t r = 1;
-    for (int t = 1; t <= b; ++t) {
-        r = r * (a - b + t) / t;
-        if (r > (1ll << 40)) return r;
-    }
-    return r;
-}
 
 template <int W>
 msm_status run_enumerate(msm_ctx* ctx, const uint64_t* S, int64_t n, int ell, int Q, int k, int h,
                          uint32_t* pairs, int64_t cap, int64_t* m_out, hipStream_t stream)
 {
-    // Blocks of nearly equal length: the first ell mod k get one extra bit.
-    std::vector<uint64_t> bm((size_t)k * MAXW, 0ull);
-    {
-        int pos = 0;
-        for (int b = 0; b < k; ++b) {
-            const int len = ell / k + (b < ell % k ? 1 : 0);
-            for (int c = pos; c < pos + len; ++c) bm[(size_t)b * MAXW + (c >> 6)] |= 1ull << (c & 63);
-            pos += len;
-        }
-    }
-    uint64_t valid[MAXW] = {0, 0, 0, 0};
-    for (int c = 0; c < ell; ++c) valid[c >> 6] |= 1ull << (c & 63);
-
-    // All h-subsets of the k blocks.
+    std::vector<uint64_t> bm;
+    uint64_t valid[MAXW];
     std::vector<Combo> combos;
-    {
-        std::vector<int> sel(h);
-        for (int t = 0; t < h; ++t) sel[t] = t;
-        while (true) {
-            Combo cb{};
-            uint64_t Bm = 0;
-            for (int t = 0; t < h; ++t) Bm |= 1ull << sel[t];
-            for (int w = 0; w < MAXW; ++w) {
-                uint64_t kw = valid[w];
-                for (int t = 0; t < h; ++t) kw &= ~bm[(size_t)sel[t] * MAXW + w];
-                cb.keep[w] = kw;
-            }
-            int lowest_kept = 0;
-            while (lowest_kept < k && ((Bm >> lowest_kept) & 1ull)) ++lowest_kept;
-            uint64_t hi = 0;
-            for (int b = lowest_kept + 1; b < k; ++b)
-                if ((Bm >> b) & 1ull) hi |= 1ull << b;
-            cb.hi = hi;
-            cb.nhi = __builtin_popcountll(hi);
-            {
-                int slot = 0;
-                for (int b = 0; b < k && slot < MAXHI; ++b)
-                    if ((hi >> b) & 1ull) {
-                        for (int w = 0; w < MAXW; ++w) cb.himask[slot][w] = bm[(size_t)b * MAXW + w];
-                        ++slot;
-                    }
-            }
-            combos.push_back(cb);
-            int t = h - 1;
-            while (t >= 0 && sel[t] == k - h + t) --t;
-            if (t < 0) break;
-            sel[t]++;
-            for (int u = t + 1; u < h; ++u) sel[u] = sel[u - 1] + 1;
-        }
-    }
+    build_tables(ell, k, h, bm, valid, combos);
     const int C = (int)combos.size();
 
     // Partition shape.
@@ -882,8 +111,8 @@ msm_status run_enumerate(msm_ctx* ctx, const uint64_t* S, int64_t n, int ell, in
         }
         {
             msm::KernelTimer kt(ctx, stream, "k_bucket");
-            hipLaunchKernelGGL((k_bucket<W>), dim3((nb + BK_GROUP - 1) / BK_GROUP, cc), dim3(BK_THREADS), 0, stream,
-                               p);
+            hipLaunchKernelGGL((k_bucket<W, BK_DIGIT, false>), dim3((nb + BK_GROUP - 1) / BK_GROUP, cc),
+                               dim3(BK_THREADS), 0, stream, p, BatchArgs{});
         }
         MSM_HIP(ctx, hipGetLastError());
         MSM_HIP(ctx, hipMemcpyAsync(ctx->host_words, d_ovfc, sizeof(uint32_t), hipMemcpyDeviceToHost, stream));

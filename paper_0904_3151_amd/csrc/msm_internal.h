@@ -63,6 +63,30 @@ msm_status profile_collect(msm_ctx* ctx);
 
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
+// Batched projection (eq. (3) for many instances in one launch).
+struct ProjInst {
+    const float* X;   // DEVICE, n rows, ldx stride
+    int64_t n;
+    int64_t ldx;
+    const float* R;   // DEVICE, d x ell
+    uint64_t* S;      // DEVICE, the instance's strings
+    uint64_t* S2;     // DEVICE, second copy (the concatenation), or NULL
+    int32_t d;
+    int32_t vec4;     // X 16-byte aligned with ldx % 4 == 0
+};
+struct ProjEntry {    // a run of rows of one instance
+    int64_t row0;
+    int32_t rows;
+    uint32_t inst;
+};
+// Rows per tile of the batched projection kernel for ell bits (entries
+// should hold a multiple of it).
+int batch_project_rows(int ell);
+// Enqueues the batched projection over `nentries` entries with a grid of
+// `grid` persistent workgroups; max_d bounds every instance's d.
+hipError_t batch_project(const ProjInst* inst, const ProjEntry* entries, int nentries, int ell, int max_d, int grid,
+                         hipStream_t stream);
+
 // Carves consecutive 256-byte-aligned pieces out of one scratch buffer.
 struct Carver {
     size_t off = 0;

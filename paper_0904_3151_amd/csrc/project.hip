@@ -27,117 +27,157 @@ constexpr int PJ_THREADS = 256;
 constexpr int PJ_WAVES = PJ_THREADS / 64;
 constexpr int PJ_LDS_BYTES = 65536;
 
+// Rl[(kc * NCB + cb) * 64 + l][j] = R[k0 + 16 kc + 4 (l / 16) + j][16 cb + l % 16]
+template <int NCB>
+__device__ __forceinline__ void stage_r(floatx4* Rl, const float* __restrict__ R, int d, int ell, int k0,
+                                        int kt_chunks)
+{
+    const int total = kt_chunks * NCB * 64;
+    for (int e = threadIdx.x; e < total; e += PJ_THREADS) {
+        const int l = e & 63;
+        const int cb = (e >> 6) % NCB;
+        const int kc = (e >> 6) / NCB;
+        const int c = cb * 16 + (l & 15);
+        const int kb = k0 + kc * 16 + 4 * (l >> 4);
+        floatx4 v;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int k = kb + j;
+            v[j] = (k < d && c < ell) ? R[(int64_t)k * ell + c] : 0.0f;
+        }
+        Rl[e] = v;
+    }
+}
+
+// One tile of 4 * RB * 16 rows starting at row_tile (rows at or above
+// row_end are skipped): z = X R on the MFMA, signs packed into S (and into
+// S2 when it is not NULL). With nkt == 1 the caller has staged all of R in
+// Rl; otherwise R is staged here kt_rows at a time. Called by every thread.
+template <int NCB, int RB>
+__device__ __forceinline__ void project_tile(const float* __restrict__ X, int64_t row_tile, int64_t row_end, int d,
+                                             int64_t ldx, const float* __restrict__ R, int ell,
+                                             uint64_t* __restrict__ S, uint64_t* __restrict__ S2, int W,
+                                             int kt_rows, int nkt, int vec4, floatx4* Rl)
+{
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int g = lane >> 4;
+    const int r16 = lane & 15;
+    const int kt_chunks = kt_rows / 16;
+    const int64_t row_w = row_tile + (int64_t)wave * RB * 16;
+    floatx4 acc[RB][NCB];
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) acc[rb][cb] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+    for (int kt = 0; kt < nkt; ++kt) {
+        const int k0 = kt * kt_rows;
+        if (nkt > 1) {
+            __syncthreads();
+            stage_r<NCB>(Rl, R, d, ell, k0, kt_chunks);
+            __syncthreads();
+        }
+        const int kcn = min(kt_chunks, (d - k0 + 15) / 16);
+        for (int kc = 0; kc < kcn; ++kc) {
+            const int kbase = k0 + kc * 16 + 4 * g;
+            floatx4 a[RB];
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) {
+                const int64_t row = row_w + rb * 16 + r16;
+                floatx4 v = floatx4{0.f, 0.f, 0.f, 0.f};
+                if (row < row_end) {
+                    const float* xr = X + row * ldx;
+                    if (vec4 && kbase + 3 < d) {
+                        v = *reinterpret_cast<const floatx4*>(xr + kbase);
+                    } else {
+#pragma unroll
+                        for (int j = 0; j < 4; ++j)
+                            if (kbase + j < d) v[j] = xr[kbase + j];
+                    }
+                }
+                a[rb] = v;
+            }
+            floatx4 b[NCB];
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) b[cb] = Rl[(kc * NCB + cb) * 64 + lane];
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                    for (int cb = 0; cb < NCB; ++cb)
+                        acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb][j], b[cb][j], acc[rb][cb], 0, 0, 0);
+        }
+    }
+
+    // Epilogue. Accumulator register i of lane l holds z for row
+    // 4 (l / 16) + i and column l % 16 of the 16 x 16 block, so
+    // ballot(acc[i] > 0) gives, in bits 16 q .. 16 q + 15, the 16 signs
+    // of row 4 q + i. Lane l then assembles word l / 16 of row l % 16.
+    const int orow = lane & 15;
+    const int oword = lane >> 4;
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) {
+        uint64_t word = 0;
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) {
+            const uint64_t m0 = __ballot(acc[rb][cb][0] > 0.0f);
+            const uint64_t m1 = __ballot(acc[rb][cb][1] > 0.0f);
+            const uint64_t m2 = __ballot(acc[rb][cb][2] > 0.0f);
+            const uint64_t m3 = __ballot(acc[rb][cb][3] > 0.0f);
+            const int i = orow & 3;
+            const uint64_t mi = i == 0 ? m0 : (i == 1 ? m1 : (i == 2 ? m2 : m3));
+            const uint64_t bits = (mi >> (16 * (orow >> 2))) & 0xFFFFull;
+            if ((cb >> 2) == oword) word |= bits << (16 * (cb & 3));
+        }
+        const int64_t row = row_w + rb * 16 + orow;
+        if (row < row_end && oword < W) {
+            S[row * W + oword] = word;
+            if (S2) S2[row * W + oword] = word;
+        }
+    }
+}
+
 template <int NCB, int RB>
 __global__ __launch_bounds__(PJ_THREADS) void k_project_f32(
     const float* __restrict__ X, int64_t n, int d, int64_t ldx, const float* __restrict__ R,
     int ell, uint64_t* __restrict__ S, int W, int kt_rows, int vec4)
 {
     extern __shared__ floatx4 Rl[];  // [kt_rows / 16][NCB][64]
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    const int g = lane >> 4;
-    const int r16 = lane & 15;
     constexpr int ROWS_PER_TILE = PJ_WAVES * RB * 16;
     const int64_t ntiles = (n + ROWS_PER_TILE - 1) / ROWS_PER_TILE;
     const int nkt = (d + kt_rows - 1) / kt_rows;
-    const int kt_chunks = kt_rows / 16;
-
-    // Rl[(kc * NCB + cb) * 64 + l][j] = R[k0 + 16 kc + 4 (l / 16) + j][16 cb + l % 16]
-    auto stage = [&](int k0) {
-        const int total = kt_chunks * NCB * 64;
-        for (int e = threadIdx.x; e < total; e += PJ_THREADS) {
-            const int l = e & 63;
-            const int cb = (e >> 6) % NCB;
-            const int kc = (e >> 6) / NCB;
-            const int c = cb * 16 + (l & 15);
-            const int kb = k0 + kc * 16 + 4 * (l >> 4);
-            floatx4 v;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int k = kb + j;
-                v[j] = (k < d && c < ell) ? R[(int64_t)k * ell + c] : 0.0f;
-            }
-            Rl[e] = v;
-        }
-    };
-
     if (nkt == 1) {
-        stage(0);
+        stage_r<NCB>(Rl, R, d, ell, 0, kt_rows / 16);
         __syncthreads();
     }
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
+        project_tile<NCB, RB>(X, tile * ROWS_PER_TILE, n, d, ldx, R, ell, S, nullptr, W, kt_rows, nkt, vec4, Rl);
+}
 
-    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const int64_t row_w = tile * ROWS_PER_TILE + (int64_t)wave * RB * 16;
-        floatx4 acc[RB][NCB];
-#pragma unroll
-        for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-            for (int cb = 0; cb < NCB; ++cb) acc[rb][cb] = floatx4{0.f, 0.f, 0.f, 0.f};
-
-        for (int kt = 0; kt < nkt; ++kt) {
-            const int k0 = kt * kt_rows;
-            if (nkt > 1) {
-                __syncthreads();
-                stage(k0);
-                __syncthreads();
-            }
-            const int kcn = min(kt_chunks, (d - k0 + 15) / 16);
-            for (int kc = 0; kc < kcn; ++kc) {
-                const int kbase = k0 + kc * 16 + 4 * g;
-                floatx4 a[RB];
-#pragma unroll
-                for (int rb = 0; rb < RB; ++rb) {
-                    const int64_t row = row_w + rb * 16 + r16;
-                    floatx4 v = floatx4{0.f, 0.f, 0.f, 0.f};
-                    if (row < n) {
-                        const float* xr = X + row * ldx;
-                        if (vec4 && kbase + 3 < d) {
-                            v = *reinterpret_cast<const floatx4*>(xr + kbase);
-                        } else {
-#pragma unroll
-                            for (int j = 0; j < 4; ++j)
-                                if (kbase + j < d) v[j] = xr[kbase + j];
-                        }
-                    }
-                    a[rb] = v;
-                }
-                floatx4 b[NCB];
-#pragma unroll
-                for (int cb = 0; cb < NCB; ++cb) b[cb] = Rl[(kc * NCB + cb) * 64 + lane];
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
-#pragma unroll
-                    for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-                        for (int cb = 0; cb < NCB; ++cb)
-                            acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb][j], b[cb][j],
-                                                                               acc[rb][cb], 0, 0, 0);
-            }
+// Batched projection: workgroups take entries (a run of rows of one
+// instance) in turn; R of the entry's instance is staged once per entry.
+template <int NCB, int RB>
+__global__ __launch_bounds__(PJ_THREADS) void k_project_batch(const msm::ProjInst* __restrict__ inst,
+                                                              const msm::ProjEntry* __restrict__ entries,
+                                                              int nentries, int ell, int W, int kt_rows)
+{
+    extern __shared__ floatx4 Rl[];
+    constexpr int ROWS_PER_TILE = PJ_WAVES * RB * 16;
+    for (int e = blockIdx.x; e < nentries; e += gridDim.x) {
+        const msm::ProjEntry en = entries[e];
+        const msm::ProjInst& in = inst[en.inst];
+        const int d = in.d;
+        const int nkt = (d + kt_rows - 1) / kt_rows;
+        if (nkt == 1) {
+            __syncthreads();  // the previous entry is done with Rl
+            stage_r<NCB>(Rl, in.R, d, ell, 0, kt_rows / 16);
+            __syncthreads();
         }
-
-        // Epilogue. Accumulator register i of lane l holds z for row
-        // 4 (l / 16) + i and column l % 16 of the 16 x 16 block, so
-        // ballot(acc[i] > 0) gives, in bits 16 q .. 16 q + 15, the 16 signs
-        // of row 4 q + i. Lane l then assembles word l / 16 of row l % 16.
-        const int orow = lane & 15;
-        const int oword = lane >> 4;
-#pragma unroll
-        for (int rb = 0; rb < RB; ++rb) {
-            uint64_t word = 0;
-#pragma unroll
-            for (int cb = 0; cb < NCB; ++cb) {
-                const uint64_t m0 = __ballot(acc[rb][cb][0] > 0.0f);
-                const uint64_t m1 = __ballot(acc[rb][cb][1] > 0.0f);
-                const uint64_t m2 = __ballot(acc[rb][cb][2] > 0.0f);
-                const uint64_t m3 = __ballot(acc[rb][cb][3] > 0.0f);
-                const int i = orow & 3;
-                const uint64_t mi = i == 0 ? m0 : (i == 1 ? m1 : (i == 2 ? m2 : m3));
-                const uint64_t bits = (mi >> (16 * (orow >> 2))) & 0xFFFFull;
-                if ((cb >> 2) == oword) word |= bits << (16 * (cb & 3));
-            }
-            const int64_t row = row_w + rb * 16 + orow;
-            if (row < n && oword < W) S[row * W + oword] = word;
-        }
+        const int64_t end = en.row0 + en.rows;
+        for (int64_t r0 = en.row0; r0 < end; r0 += ROWS_PER_TILE)
+            project_tile<NCB, RB>(in.X, r0, end, d, in.ldx, in.R, ell, in.S, in.S2, W, kt_rows, nkt, in.vec4, Rl);
     }
 }
 
@@ -202,3 +242,55 @@ extern "C" msm_status msm_project(msm_ctx* ctx, const float* X, int64_t n, int32
         default: return launch_project<16>(ctx, X, n, d, ldx, R, ell, S, s);
     }
 }
+
+namespace {
+
+template <int NCB>
+hipError_t launch_batch(const msm::ProjInst* inst, const msm::ProjEntry* entries, int nentries, int ell,
+                        int max_d, int grid, hipStream_t stream)
+{
+    constexpr int RB = NCB <= 4 ? 4 : (NCB <= 8 ? 2 : 1);
+    const int W = (ell + 63) / 64;
+    const int dpad = (max_d + 15) / 16 * 16;
+    const int max_chunks = PJ_LDS_BYTES / (NCB * 64 * 16);
+    const int kt_rows = min(dpad, max_chunks * 16);
+    const size_t lds = (size_t)(kt_rows / 16) * NCB * 64 * sizeof(floatx4);
+    hipLaunchKernelGGL((k_project_batch<NCB, RB>), dim3((unsigned)grid), dim3(PJ_THREADS), lds, stream, inst,
+                       entries, nentries, ell, W, kt_rows);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+namespace msm {
+
+int batch_project_rows(int ell)
+{
+    const int ncb = (ell + 15) / 16;
+    return PJ_WAVES * 16 * (ncb <= 4 ? 4 : (ncb <= 8 ? 2 : 1));
+}
+
+hipError_t batch_project(const ProjInst* inst, const ProjEntry* entries, int nentries, int ell, int max_d, int grid,
+                         hipStream_t stream)
+{
+    switch ((ell + 15) / 16) {
+        case 1: return launch_batch<1>(inst, entries, nentries, ell, max_d, grid, stream);
+        case 2: return launch_batch<2>(inst, entries, nentries, ell, max_d, grid, stream);
+        case 3: return launch_batch<3>(inst, entries, nentries, ell, max_d, grid, stream);
+        case 4: return launch_batch<4>(inst, entries, nentries, ell, max_d, grid, stream);
+        case 5: return launch_batch<5>(inst, entries, nentries, ell, max_d, grid, stream);
+        case 6: return launch_batch<6>(inst, entries, nentries, ell, max_d, grid, stream);
+        case 7: return launch_batch<7>(inst, entries, nentries, ell, max_d, grid, stream);
+        case 8: return launch_batch<8>(inst, entries, nentries, ell, max_d, grid, stream);
+        case 9: return launch_batch<9>(inst, entries, nentries, ell, max_d, grid, stream);
+        case 10: return launch_batch<10>(inst, entries, nentries, ell, max_d, grid, stream);
+        case 11: return launch_batch<11>(inst, entries, nentries, ell, max_d, grid, stream);
+        case 12: return launch_batch<12>(inst, entries, nentries, ell, max_d, grid, stream);
+        case 13: return launch_batch<13>(inst, entries, nentries, ell, max_d, grid, stream);
+        case 14: return launch_batch<14>(inst, entries, nentries, ell, max_d, grid, stream);
+        case 15: return launch_batch<15>(inst, entries, nentries, ell, max_d, grid, stream);
+        default: return launch_batch<16>(inst, entries, nentries, ell, max_d, grid, stream);
+    }
+}
+
+}  // namespace msm

@@ -138,6 +138,23 @@ def projection_matrices(d: int, ell: int, Q: int, seed: int) -> np.ndarray:
     return np.stack([projection_matrix(d, ell, seed + 100 * q) for q in range(Q)])
 
 
+def batched_instances(count: int, seed: int, n_lo: int = 1000, n_hi: int = 200_000,
+                      ds=(32, 64, 128), ell: int = 64, sigma: float = 0.2):
+    """Sizes and inputs of independent instances for the batched form:
+    n log-uniform in [n_lo, n_hi], d uniform over ds, Gaussian-mixture rows
+    with n / 100 clusters (at least one) and per-coordinate sigma, and an
+    N(0, 1) projection matrix per instance. Returns a list of (X, R)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ns = np.exp(rng.uniform(np.log(n_lo), np.log(n_hi), count)).astype(np.int64)
+    dd = rng.choice(np.asarray(ds), count)
+    out = []
+    for i in range(count):
+        n, d = int(ns[i]), int(dd[i])
+        X, _ = gaussian_mixture(n, d, max(1, n // 100), sigma, seed=seed * 1000 + i)
+        out.append((X, projection_matrix(d, ell, seed=seed * 1000 + 500_000 + i)))
+    return out
+
+
 def mlp_initial_parameters(d: int, hid: int, ell: int, seed: int) -> np.ndarray:
     """Initial weights of the learned projection, packed FP32
     [W1 (d x hid) | b1 | W2 (hid x ell) | b2]: W ~ N(0, 2 / fan_in), b = 0."""

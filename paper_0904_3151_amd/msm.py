@@ -42,11 +42,29 @@ EXPORTS = ("msm_version", "msm_create", "msm_destroy", "msm_last_error",
            "msm_project", "msm_project_lowp", "msm_enumerate_pairs", "msm_enumerate_replicates",
            "msm_verify", "msm_bruteforce_eps",
            "msm_project_mlp", "msm_mlp_loss_grad", "msm_mlp_adam", "msm_mlp_train",
+           "msm_batch_create", "msm_batch_run", "msm_batch_launch_graph", "msm_batch_tuning",
+           "msm_batch_destroy",
            "msm_profile_enable", "msm_profile_reset", "msm_profile_read")
 
 
 class KernelTime(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double)]
+
+
+class Instance(ctypes.Structure):
+    """msm_instance: one problem of a batch (device pointers)."""
+    _fields_ = [("X", ctypes.c_void_p), ("R", ctypes.c_void_p), ("S", ctypes.c_void_p),
+                ("pairs", ctypes.c_void_p), ("n", ctypes.c_int64), ("ldx", ctypes.c_int64),
+                ("cap", ctypes.c_int64), ("d", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class BatchConfig(ctypes.Structure):
+    _fields_ = [("bucket_target", ctypes.c_int32), ("digit_bits", ctypes.c_int32),
+                ("buckets_per_group", ctypes.c_int32), ("ms", ctypes.c_float)]
+
+    def as_dict(self):
+        return {"bucket_target": self.bucket_target, "digit_bits": self.digit_bits,
+                "buckets_per_group": self.buckets_per_group, "ms": round(float(self.ms), 4)}
 
 
 class MSMError(RuntimeError):
@@ -95,6 +113,17 @@ def _load():
     lib.msm_mlp_train.argtypes = [vp, vp, i64, i32, i64, vp, vp, vp, i32, i32, vp, vp, i64, i32, i64, i64,
                                   f32, f32, f32, ctypes.POINTER(f32), vp]
     lib.msm_mlp_train.restype = i32
+    lib.msm_batch_create.argtypes = [vp, ctypes.POINTER(Instance), i32, i32, i32, i32, i32, ctypes.POINTER(vp), vp]
+    lib.msm_batch_create.restype = i32
+    lib.msm_batch_run.argtypes = [vp, vp, vp]
+    lib.msm_batch_run.restype = i32
+    lib.msm_batch_launch_graph.argtypes = [vp, vp, vp]
+    lib.msm_batch_launch_graph.restype = i32
+    lib.msm_batch_tuning.argtypes = [vp, ctypes.POINTER(BatchConfig), ctypes.POINTER(BatchConfig), i32,
+                                     ctypes.POINTER(i32)]
+    lib.msm_batch_tuning.restype = i32
+    lib.msm_batch_destroy.argtypes = [vp]
+    lib.msm_batch_destroy.restype = None
     lib.msm_profile_enable.argtypes = [vp, i32]
     lib.msm_profile_enable.restype = i32
     lib.msm_profile_reset.argtypes = [vp]
@@ -401,6 +430,78 @@ def msm_mlp_train(ctx: Context, X: torch.Tensor, params: torch.Tensor, m: torch.
                             int(first_step), float(lr), float(h), float(lam), losses, _stream(stream))
     _check(ctx, st)
     return [float(losses[i]) for i in range(int(steps))]
+
+
+class Batch:
+    """A plan for many independent instances (msm_batch_create): strings by
+    eq. (3) and Hamming pairs of every instance in one enqueue.
+
+    ``X_list`` and ``R_list`` hold float32 device tensors (n_i, d_i) and
+    (d_i, ell); ``caps`` the pair capacity of each instance. The plan owns
+    the output tensors ``S[i]`` (int64 (n_i, W)) and ``pairs[i]`` (int32
+    (cap_i, 2)); after a run, instance i's pairs are pairs[i][:m[i]].
+    """
+
+    def __init__(self, ctx: Context, X_list, R_list, ell: int, k: int, h: int, caps, autotune: bool = True,
+                 stream=None):
+        self.ctx = ctx
+        self.ell, self.k, self.h = int(ell), int(k), int(h)
+        count = len(X_list)
+        assert count == len(R_list) == len(caps) and count > 0
+        W = _words(ell)
+        self.X = list(X_list)
+        self.R = list(R_list)
+        self.S, self.pairs = [], []
+        arr = (Instance * count)()
+        for i, (X, R, cap) in enumerate(zip(self.X, self.R, caps)):
+            assert X.dtype == torch.float32 and X.dim() == 2 and X.is_cuda
+            assert X.shape[0] == 0 or X.stride(1) == 1
+            assert R.dtype == torch.float32 and R.is_contiguous() and R.shape == (X.shape[1], ell)
+            n, d = X.shape
+            S = torch.empty((n, W), dtype=torch.int64, device=X.device)
+            P = torch.empty((max(1, int(cap)), 2), dtype=torch.int32, device=X.device)
+            self.S.append(S)
+            self.pairs.append(P)
+            arr[i] = Instance(X.data_ptr() if n else None, R.data_ptr(), S.data_ptr() if n else None, P.data_ptr(),
+                              n, X.stride(0) if n > 0 else d, int(cap), d, 0)
+        self.count = count
+        self._arr = arr
+        h_ = ctypes.c_void_p()
+        st = _lib.msm_batch_create(ctx.handle, arr, count, self.ell, self.k, self.h, int(bool(autotune)),
+                                   ctypes.byref(h_), _stream(stream))
+        _check(ctx, st)
+        self._h = h_
+        self.m = torch.zeros(count, dtype=torch.int64, device=self.X[0].device)
+
+    def run(self, stream=None, graph: bool = False) -> torch.Tensor:
+        """Enqueue one run (as one captured graph when ``graph``); returns the
+        device tensor of per-instance pair counts."""
+        fn = _lib.msm_batch_launch_graph if graph else _lib.msm_batch_run
+        _check(self.ctx, fn(self._h, ctypes.c_void_p(self.m.data_ptr()), _stream(stream)))
+        return self.m
+
+    def instance_pairs(self, i: int, m: int) -> torch.Tensor:
+        return self.pairs[i][: min(int(m), self.pairs[i].shape[0])]
+
+    def tuning(self) -> dict:
+        chosen = BatchConfig()
+        nt = ctypes.c_int32(0)
+        _check(self.ctx, _lib.msm_batch_tuning(self._h, ctypes.byref(chosen), None, 0, ctypes.byref(nt)))
+        tried = (BatchConfig * max(1, nt.value))()
+        _check(self.ctx, _lib.msm_batch_tuning(self._h, None, tried, nt.value, None))
+        return {"chosen": chosen.as_dict(), "tried": [tried[i].as_dict() for i in range(nt.value)]}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            torch.cuda.synchronize()
+            _lib.msm_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def msm_profile_enable(ctx: Context, enable: bool = True):

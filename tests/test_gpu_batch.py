@@ -1,0 +1,161 @@
+"""Parity of the batched form (msm_batch_*): every instance's strings agree
+with the FP64 projection except inside the rounding band, and every
+instance's pair list equals the definition {(i, j): i < j, HamDist <= h} of
+its own strings exactly, eagerly and on every replay of the captured graph."""
+import numpy as np
+import pytest
+import torch
+
+from helpers import PROJ_BAND, announce, codes, to_np_pairs, to_np_strings
+from oracle import oracle as O
+from paper_0904_3151_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def make_instances(count, seed, n_lo, n_hi, ell, extra=()):
+    inst = I.batched_instances(count, seed, n_lo=n_lo, n_hi=n_hi, ds=(32, 64, 128, 33), ell=ell)
+    return list(inst) + list(extra)
+
+
+def upload(inst, strided_every=0):
+    Xs, Rs = [], []
+    for i, (X, R) in enumerate(inst):
+        n, d = X.shape
+        if strided_every and i % strided_every == 0 and n > 0:
+            big = torch.zeros((n, d + 3), dtype=torch.float32, device="cuda")
+            big[:, :d] = torch.from_numpy(X)
+            Xs.append(big[:, :d])          # ldx = d + 3
+        else:
+            Xs.append(torch.from_numpy(np.ascontiguousarray(X)).cuda().reshape(n, d))
+        Rs.append(torch.from_numpy(R).cuda())
+    return Xs, Rs
+
+
+def check_batch(b, inst, ell, h, m, strings=True):
+    m = m.cpu().numpy()
+    for i, (X, R) in enumerate(inst):
+        S = to_np_strings(b.S[i]) if X.shape[0] else np.zeros((0, (ell + 63) // 64), np.uint64)
+        if strings and X.shape[0]:
+            So, Z, xn = O.project(X, R, want_z=True)
+            bad = I.unpack_bits(S, ell) != I.unpack_bits(So, ell)
+            assert not (bad & ~(np.abs(Z) < PROJ_BAND * xn[:, None])).any(), f"instance {i}: bits outside band"
+        want = codes(O.hamming_pairs(S, h)) if X.shape[0] > 1 else np.zeros(0, np.uint64)
+        got = codes(to_np_pairs(b.instance_pairs(i, m[i])))
+        assert m[i] == want.size, (i, m[i], want.size)
+        assert np.array_equal(got, want), f"instance {i}: pair set differs"
+
+
+def identical_rows(n, d, seed):
+    rng = np.random.default_rng(seed)
+    row = rng.standard_normal(d).astype(np.float32)
+    X = np.repeat(row[None, :], n, axis=0)
+    X[n // 2:] += 1e-3 * rng.standard_normal((n - n // 2, d)).astype(np.float32)  # a second, near-identical group
+    return X
+
+
+@pytest.mark.parametrize("ell,k,h,tune", [(64, 5, 3, True), (64, 5, 3, False), (128, 8, 4, False),
+                                          (130, 7, 2, False)])
+def test_batch_matches_definition(msm, ctx, ell, k, h, tune):
+    d = 48
+    extra = [
+        (np.zeros((0, d), np.float32), I.projection_matrix(d, ell, 1)),        # empty instance
+        (np.ones((1, d), np.float32), I.projection_matrix(d, ell, 2)),         # one point
+        (I.gaussian_mixture(2, d, 1, 0.01, 3)[0], I.projection_matrix(d, ell, 3)),
+        # 1500 nearly identical rows: buckets above the LDS capacity
+        (identical_rows(1500, d, 4), I.projection_matrix(d, ell, 4)),
+    ]
+    inst = make_instances(36, seed=ell + k, n_lo=10, n_hi=4000, ell=ell, extra=extra)
+    Xs, Rs = upload(inst, strided_every=5)
+    caps = [X.shape[0] * (X.shape[0] - 1) // 2 + 16 for X, _ in inst]
+    announce("batch", ell, k, h, tune, len(inst))
+    b = msm.Batch(ctx, Xs, Rs, ell, k, h, caps, autotune=tune)
+    m = b.run()
+    torch.cuda.synchronize()
+    check_batch(b, inst, ell, h, m)
+    if tune:
+        t = b.tuning()
+        assert len(t["tried"]) == 18
+        assert t["chosen"]["ms"] == min(c["ms"] for c in t["tried"])
+    b.close()
+
+
+def test_batch_graph_replays(msm, ctx):
+    ell, k, h = 64, 5, 3
+    inst = make_instances(24, seed=7, n_lo=100, n_hi=3000, ell=ell,
+                          extra=[(identical_rows(1300, 32, 9), I.projection_matrix(32, ell, 9))])
+    Xs, Rs = upload(inst)
+    caps = [X.shape[0] ** 2 // 2 + 16 for X, _ in inst]
+    announce("batch graph", len(inst))
+    b = msm.Batch(ctx, Xs, Rs, ell, k, h, caps, autotune=False)
+    m = b.run().clone()
+    torch.cuda.synchronize()
+    eager = [codes(to_np_pairs(b.instance_pairs(i, m[i].item()))) for i in range(len(inst))]
+    check_batch(b, inst, ell, h, m, strings=False)
+    for rep in range(3):
+        # the program's own eager work between replays
+        junk = torch.randn(1 << 20, device="cuda")
+        junk.mul_(2.0).sum().item()
+        for P in b.pairs:
+            P.fill_(-1)
+        announce("batch graph replay", rep)
+        mg = b.run(graph=True)
+        torch.cuda.synchronize()
+        assert torch.equal(mg.cpu(), m.cpu())
+        for i in range(len(inst)):
+            assert np.array_equal(codes(to_np_pairs(b.instance_pairs(i, mg[i].item()))), eager[i]), (rep, i)
+    b.close()
+
+
+def test_batch_capacity_and_count_only(msm, ctx):
+    ell, k, h = 64, 5, 3
+    inst = make_instances(6, seed=11, n_lo=500, n_hi=2000, ell=ell)
+    Xs, Rs = upload(inst)
+    b0 = msm.Batch(ctx, Xs, Rs, ell, k, h, [1 << 20] * len(inst), autotune=False)
+    full = b0.run().cpu().numpy()
+    sets = [codes(to_np_pairs(b0.instance_pairs(i, full[i]))) for i in range(len(inst))]
+    b0.close()
+    caps = [int(v // 2) for v in full]
+    caps[0] = 0  # count only
+    b = msm.Batch(ctx, Xs, Rs, ell, k, h, caps, autotune=False)
+    m = b.run().cpu().numpy()
+    assert np.array_equal(m, full)
+    for i in range(1, len(inst)):
+        got = codes(to_np_pairs(b.pairs[i][: caps[i]]))
+        assert got.size == caps[i] and np.isin(got, sets[i]).all() and np.unique(got).size == got.size
+    b.close()
+
+
+def test_batch_matches_single_path_at_scale(msm, ctx):
+    """Instances of the batched workload's size range (n up to 200k): the
+    batch gives each instance exactly the pairs msm_enumerate_pairs gives
+    for the same strings."""
+    ell, k, h = 64, 5, 3
+    inst = I.batched_instances(12, seed=1004, ell=ell)
+    Xs, Rs = upload(inst)
+    caps = [60 * X.shape[0] for X, _ in inst]
+    announce("batch scale", [X.shape[0] for X, _ in inst])
+    b = msm.Batch(ctx, Xs, Rs, ell, k, h, caps, autotune=True)
+    m = b.run().cpu().numpy()
+    torch.cuda.synchronize()
+    for i in range(len(inst)):
+        assert m[i] <= caps[i]
+        P, mi = msm.enumerate_pairs(ctx, b.S[i], ell, k, h)
+        assert mi == m[i]
+        assert np.array_equal(codes(to_np_pairs(b.instance_pairs(i, m[i]))), codes(to_np_pairs(P))), i
+    b.close()
+
+
+def test_batch_invalid(msm, ctx):
+    import ctypes
+    X = torch.zeros((4, 8), device="cuda")
+    R = torch.zeros((8, 64), device="cuda")
+    with pytest.raises(msm.MSMError):
+        msm.Batch(ctx, [X], [R], 64, 3, 3, [10])          # h >= k
+    arr = (msm.Instance * 1)()
+    arr[0] = msm.Instance(None, R.data_ptr(), None, None, 4, 8, 0, 8, 0)   # n > 0 without X
+    h_ = ctypes.c_void_p()
+    st = msm.lib().msm_batch_create(ctx.handle, arr, 1, 64, 5, 3, 0, ctypes.byref(h_), None)
+    assert st == msm.MSM_E_INVALID and not h_.value
+    st = msm.lib().msm_batch_create(ctx.handle, arr, 0, 64, 5, 3, 0, ctypes.byref(h_), None)
+    assert st == msm.MSM_E_INVALID
