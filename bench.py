@@ -10,11 +10,14 @@ and the missing-edge ratio is defined.
 
 Other workloads: ``--workload precision`` (4M sparse cosine rows, FP32 /
 BF16 / FP8 projections) and ``--workload learned`` (2M mixture points, the
-learned projection trained on the GPU against random projection).
+learned projection trained on the GPU against random projection) and
+``--workload batched`` (512 independent instances in one captured graph)
+and ``--workload sweep`` (output sensitivity: n from 125k to 2M, and the
+all-identical worst case).
 
 Usage: python bench.py [--steps K] [--warmup W] [--sigma-mode coord|radius]
                        [--cpu-sample N | --no-cpu-baseline] [--no-second-reading]
-                       [--workload paper|precision|learned] [--epochs E]
+                       [--workload paper|precision|learned|batched|sweep] [--epochs E]
 """
 import argparse
 import json
@@ -34,6 +37,45 @@ METRIC = "points/s + edges/s at n=1M,d=128,ℓ=128,h≤4; missing-edge ratio vs 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` on `workload` from the stored
+    rocprofv3 counter runs (FETCH_SIZE and WRITE_SIZE, each scaled by the
+    same counter's reading for a copy of known size), or None when there is
+    no such measurement or the kernel's source has changed since."""
+    import hashlib
+    try:
+        with open(TRAFFIC_FILE) as f:
+            entries = json.load(f)["entries"]
+    except (OSError, ValueError, KeyError):
+        return None
+    for e in entries:
+        if e.get("kernel") != kernel or e.get("workload") != workload:
+            continue
+        try:
+            with open(os.path.join(ROOT, e["source"]), "rb") as f:
+                if hashlib.sha256(f.read()).hexdigest() != e["sha256"]:
+                    return None
+        except OSError:
+            return None
+        return e["bytes_per_launch"]
+    return None
+
+
+def copy_calibration(nbytes, reps=3):
+    """Device-to-device copies of `nbytes` (the counters' reference)."""
+    import torch
+    n = nbytes // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": n * 4, "reps": reps}), flush=True)
 
 
 def algorithmic(kernel, w, n, C, mH, mE, W):
@@ -263,8 +305,9 @@ def run_mixture(msm, ctx, w, X, Xd, project, steps, warmup, judge_sub=None):
     return res
 
 
-def roofline_of(res, w, n, W):
-    """Roofline object of the kernel with the most time per step."""
+def roofline_of(res, w, n, W, tag):
+    """Roofline object of the kernel with the most time per step; `tag`
+    names the workload variant for the stored traffic measurement."""
     phase = res["phase"]
     dom = max(phase, key=lambda k: phase[k]["ms_per_step"])
     alg = algorithmic(dom, w, n, res["combinations"], res["hamming_pairs"], res["eps_pairs"], W)
@@ -274,8 +317,11 @@ def roofline_of(res, w, n, W):
     amount, unit, bound = alg
     achieved = amount / (phase[dom]["avg_ms"] / 1e3)
     peak = {"mfma": FP32_MFMA_PEAK_TFLOPS, "mfma_bf16": BF16_MFMA_PEAK_TFLOPS}.get(bound, HBM_PEAK_GBS)
+    traffic = measured_traffic(dom, tag) if bound == "hbm" else None
     return {"kernel": dom, "bound": "mfma" if bound.startswith("mfma") else bound, "achieved": round(achieved, 2),
-            "peak": peak, "unit": unit, "frac": round(achieved / peak, 4), "traffic": None}
+            "peak": peak, "unit": unit, "frac": round(achieved / peak, 4),
+            "traffic": round(traffic / 1e9, 4) if traffic is not None else None,
+            "traffic_unit": "GB per launch", "algorithmic_per_launch": round(amount, 4)}
 
 
 def compact(res):
@@ -347,7 +393,170 @@ def run_learned(args):
                         "train_s": round(t_train, 2), "loss_first": losses[0],
                         "loss_last20": float(np.mean(losses[-20:])), "config": vars(cfg)},
            "learned": compact(learned), "random_lsh": compact(rand),
-           "roofline": roofline_of(learned, w, n, W), "roofline_projection": mlp_roof, "cpu_baseline": None}
+           "roofline": roofline_of(learned, w, n, W, f"{w.name}:radius:learned"), "roofline_projection": mlp_roof,
+           "cpu_baseline": None}
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+def run_batched(args):
+    """The batched form: 512 independent instances (n log-uniform in
+    [1000, 200000], d in {32, 64, 128}, Gaussian mixtures with n / 100
+    clusters and sigma 0.2, ell = 64, k = 5, h = 3), projected and enumerated
+    by one captured graph per step. Also timed: the same run enqueued
+    eagerly (with per-kernel times) and the instances one by one through
+    msm_project + msm_enumerate_pairs."""
+    import numpy as np
+    import torch
+
+    from paper_0904_3151_amd import inputs as I
+    from paper_0904_3151_amd import msm
+
+    ell, k, h, count = 64, 5, 3, 512
+    log("generating 512 instances")
+    inst = I.batched_instances(count, seed=1004, ell=ell)
+    dev = torch.device("cuda:0")
+    Xs = [torch.from_numpy(X).to(dev) for X, _ in inst]
+    Rs = [torch.from_numpy(R).to(dev) for _, R in inst]
+    ns = np.array([X.shape[0] for X, _ in inst], dtype=np.int64)
+    ds = np.array([X.shape[1] for X, _ in inst], dtype=np.int64)
+    N = int(ns.sum())
+    del inst
+    ctx = msm.Context(0)
+    caps = [int(40 * n) for n in ns]
+    t0 = time.perf_counter()
+    b = msm.Batch(ctx, Xs, Rs, ell, k, h, caps, autotune=True)
+    torch.cuda.synchronize()
+    t_plan = time.perf_counter() - t0
+    tuning = b.tuning()
+    log(f"plan + autotune {t_plan:.2f} s, chosen {tuning['chosen']}")
+    for _ in range(args.warmup):
+        b.run(graph=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        m = b.run(graph=True)
+    torch.cuda.synchronize()
+    ms_graph = (time.perf_counter() - t0) * 1e3 / args.steps
+    m = m.cpu().numpy()
+    overflow = int((m > np.array(caps)).sum())
+    # eager runs with per-kernel event timing
+    msm.msm_profile_reset(ctx)
+    msm.msm_profile_enable(ctx, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        b.run()
+    torch.cuda.synchronize()
+    ms_eager = (time.perf_counter() - t0) * 1e3 / args.steps
+    msm.msm_profile_enable(ctx, False)
+    prof = msm.msm_profile_read(ctx)
+    phase = {name: {"launches": l, "avg_ms": t / max(l, 1), "ms_per_step": t / args.steps}
+             for name, (l, t) in prof.items()}
+    # the instances one at a time through the single-problem entry points
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    same = True
+    for i in range(count):
+        S = msm.msm_project(ctx, Xs[i], Rs[i])
+        _, mi = msm.msm_enumerate_pairs(ctx, S, ell, k, h, cap=0)
+        same &= (mi == m[i])
+    torch.cuda.synchronize()
+    ms_seq = (time.perf_counter() - t0) * 1e3
+    C = 10
+    dom = max(phase, key=lambda q: phase[q]["ms_per_step"]) if phase else None
+    roof = None
+    if dom:
+        mH = int(m.sum())
+        per = {"k_bpart_count": N * C * 8, "k_bpart_scatter": N * C * 16, "k_bucket_batch": N * C * 16 + mH * 8,
+               "k_project_batch": int((ns * ds).sum()) * 4 + N * 16}
+        if dom in per:
+            ach = per[dom] / 1e9 / (phase[dom]["avg_ms"] / 1e3)
+            roof = {"kernel": dom, "bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None}
+    out = {"metric": METRIC, "value": round(N / (ms_graph / 1e3), 1), "unit": "points/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_graph, 4),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic Gaussian mixtures, one per instance",
+           "config": {"workload": "batched-512-instances-l64-k5-h3", "instances": count, "total_points": N,
+                      "n_range": [int(ns.min()), int(ns.max())], "ell": ell, "k": k, "h": h},
+           "hamming_pairs": int(m.sum()), "hamming_pairs_per_s": round(float(m.sum()) / (ms_graph / 1e3), 1),
+           "instances_over_capacity": overflow,
+           "ms_per_step_eager": round(ms_eager, 4), "ms_one_by_one": round(ms_seq, 2),
+           "one_by_one_counts_match": bool(same), "plan_and_tune_s": round(t_plan, 2), "autotune": tuning,
+           "kernels": {q: {kk: round(vv, 4) if isinstance(vv, float) else vv for kk, vv in v.items()}
+                       for q, v in sorted(phase.items())},
+           "roofline": roof, "cpu_baseline": None}
+    print(json.dumps(out), flush=True)
+    b.close()
+    ctx.close()
+
+
+def run_sweep(args):
+    """Output sensitivity (Sections 2.3 and 5.4): whole steps on the
+    paper-scale mixture (radius reading, 5000 clusters) at n = 125k ... 2M,
+    with time per 10k output pairs, and the worst case of Section 2.3 where
+    all strings are identical and every pair is output."""
+    import numpy as np
+    import torch
+
+    from paper_0904_3151_amd import inputs as I
+    from paper_0904_3151_amd import msm
+
+    w = I.PAPER_SCALE
+    dev = torch.device("cuda:0")
+    ctx = msm.Context(0)
+    R = torch.from_numpy(I.projection_matrix(w.d, w.ell, w.seed_r)).to(dev)
+    rows = []
+    for n in (125_000, 250_000, 500_000, 1_000_000, 2_000_000):
+        X, _ = I.gaussian_mixture(n, w.d, w.n_centres, w.sigma, w.seed_data, "radius")
+        Xd = torch.from_numpy(X).to(dev)
+        del X
+        S = torch.empty((n, 2), dtype=torch.int64, device=dev)
+        msm.msm_project(ctx, Xd, R, S)
+        _, mH = msm.msm_enumerate_pairs(ctx, S, w.ell, w.k, w.h, cap=0)
+        pairs = torch.empty((int(mH * 1.05) + 1024, 2), dtype=torch.int32, device=dev)
+        out = torch.empty_like(pairs)
+        for _ in range(args.warmup):
+            msm.msm_project(ctx, Xd, R, S)
+            P, mH = msm.msm_enumerate_pairs(ctx, S, w.ell, w.k, w.h, pairs=pairs)
+            msm.msm_verify(ctx, Xd, P, w.metric, w.eps, out=out)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            msm.msm_project(ctx, Xd, R, S)
+            P, mH = msm.msm_enumerate_pairs(ctx, S, w.ell, w.k, w.h, pairs=pairs)
+            _, mE = msm.msm_verify(ctx, Xd, P, w.metric, w.eps, out=out)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        rows.append({"n": n, "ms_per_step": round(ms, 4), "hamming_pairs": int(mH), "eps_pairs": int(mE),
+                     "ms_per_10k_pairs": round(ms / max(mE, 1) * 1e4, 6), "points_per_s": round(n / ms * 1e3, 1)})
+        log(rows[-1])
+        del Xd, S, pairs, out, P
+        torch.cuda.empty_cache()
+    # worst case: n identical strings, all n (n - 1) / 2 pairs are output
+    n = 20_000
+    S = torch.zeros((n, 2), dtype=torch.int64, device=dev)
+    _, m = msm.msm_enumerate_pairs(ctx, S, w.ell, w.k, w.h, cap=0)
+    pairs = torch.empty((m, 2), dtype=torch.int32, device=dev)
+    msm.msm_enumerate_pairs(ctx, S, w.ell, w.k, w.h, pairs=pairs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        msm.msm_enumerate_pairs(ctx, S, w.ell, w.k, w.h, pairs=pairs)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    worst = {"n": n, "pairs": int(m), "expected": n * (n - 1) // 2, "ms": round(ms, 3),
+             "pairs_per_s": round(m / ms * 1e3, 1)}
+    log(worst)
+    ratios = [round(rows[i + 1]["ms_per_step"] / rows[i]["ms_per_step"], 3) for i in range(len(rows) - 1)]
+    last = rows[-2]
+    out = {"metric": METRIC, "value": last["points_per_s"], "unit": "points/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": last["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic Gaussian mixture, sigma_mode=radius",
+           "config": {"workload": "sweep-mixture-d128-l128-k8-h4-radius", "k": w.k, "h": w.h, "ell": w.ell},
+           "sweep": rows, "time_ratio_when_n_doubles": ratios, "all_identical": worst,
+           "roofline": None, "cpu_baseline": None}
     print(json.dumps(out), flush=True)
     ctx.close()
 
@@ -363,20 +572,33 @@ def main():
     ap.add_argument("--no-second-reading", action="store_true",
                     help="skip the run under the other reading of sigma")
     ap.add_argument("--epochs", type=int, default=10, help="training epochs of the learned form")
-    ap.add_argument("--workload", default="paper", choices=["paper", "precision", "learned"],
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only copy BYTES on the device a few times (reference for the HBM counters)")
+    ap.add_argument("--workload", default="paper", choices=["paper", "precision", "learned", "batched", "sweep"],
                     help="paper: the 1M mixture (default); precision: 4M sparse rows, FP32/BF16/FP8; "
-                         "learned: 2M mixture, trained network vs random projection")
+                         "learned: 2M mixture, trained network vs random projection; "
+                         "batched: 512 instances in one captured graph; "
+                         "sweep: n from 125k to 2M and the all-identical worst case")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py runs on one GPU only: the MSM path here is built and measured on a single "
               "MI355X (see the design notes for how it would shard).", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     if args.workload == "precision":
         run_precision(args)
         return
     if args.workload == "learned":
         run_learned(args)
+        return
+    if args.workload == "batched":
+        run_batched(args)
+        return
+    if args.workload == "sweep":
+        run_sweep(args)
         return
 
     import torch
@@ -393,7 +615,7 @@ def main():
     Rd = torch.from_numpy(R).to(dev)
     ctx = msm.Context(0)
     res = run_mixture(msm, ctx, w, X, Xd, lambda S: msm.msm_project(ctx, Xd, Rd, S), args.steps, args.warmup)
-    roof = roofline_of(res, w, n, W)
+    roof = roofline_of(res, w, n, W, f"{w.name}:{args.sigma_mode}")
     second = None
     if not args.no_second_reading:
         other = "radius" if args.sigma_mode == "coord" else "coord"
@@ -405,7 +627,7 @@ def main():
                          args.warmup)
         second = compact(r2)
         second["sigma_mode"] = other
-        second["roofline"] = roofline_of(r2, w, n, W)
+        second["roofline"] = roofline_of(r2, w, n, W, f"{w.name}:{other}")
         del X2d
         torch.cuda.empty_cache()
 

@@ -3,8 +3,9 @@ products, FP32 accumulation and FP32 recompute inside the margin) with the
 FP64 oracle.
 
 A bit may differ from the FP64 sign only where the product error can reach
-|z|. With A = sum_t |x_t| |r_t|, rounding to BF16 (8-bit significand) moves
-each product by at most (2^-8 + 2^-18) of its magnitude and the FP32
+|z|. With A = sum_t |x_t| |r_t|, rounding both operands to BF16 (8-bit
+significand, unit roundoff u = 2^-8) moves each product by at most
+2u + u^2 = 2^-7 + 2^-16 of its magnitude and the FP32
 accumulation adds at most d 2^-24 A. FP8 e4m3 (4-bit significand) moves each
 scaled value by at most 2^-4 of itself, or 2^-10 of the scale in the
 subnormal range. Entries recomputed in FP32 can differ only inside the FP32
@@ -28,7 +29,8 @@ def error_bound(X, R, dtype):
     A = X64 @ R64
     d = X.shape[1]
     if dtype == "bf16":
-        return (2.0 ** -8 + 2.0 ** -18) * 1.01 * A + d * 2.0 ** -23 * A
+        # both operands rounded to 8 significant bits: u = 2^-8, (1+u)^2 - 1
+        return (2.0 ** -7 + 2.0 ** -16) * 1.01 * A + d * 2.0 ** -23 * A
     ia = 240.0 / np.maximum(X64.max(axis=1), 1e-300)
     ib = 240.0 / np.maximum(R64.max(axis=0), 1e-300)
     sub_x = (2.0 ** -10 / ia)[:, None] * R64.sum(axis=0)[None, :]
