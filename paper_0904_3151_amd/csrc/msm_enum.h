@@ -485,14 +485,14 @@ template <int W, int DIGIT, bool BATCH>
 __global__ __launch_bounds__(BK_THREADS) void k_bucket(Params p, BatchArgs ba)
 {
     constexpr int BINS = 1 << DIGIT;
+    // hist holds the digit counts, then (for bins that form runs) the run's
+    // first slot in the member arrays | run index << 16
     __shared__ uint32_t hist[BINS];
-    __shared__ uint16_t binStart[BINS];
-    __shared__ uint16_t binRun[BINS];
-    __shared__ uint64_t keysB[BK_CAP];
+    __shared__ uint32_t idxB[BK_CAP];
     __shared__ uint64_t sl[BK_CAP * W];
     __shared__ uint16_t runS[BK_CAP / 2];
     __shared__ uint16_t runL[BK_CAP / 2];
-    __shared__ unsigned long long runVar[BK_CAP / 2 * W];  // bits that vary inside the run
+    __shared__ unsigned long long runBlk[BK_CAP / 2];  // blocks of hi that vary inside the run
     __shared__ uint16_t liveS[BK_CAP / 2];
     __shared__ uint16_t liveL[BK_CAP / 2];
     __shared__ uint32_t liveP[BK_CAP / 2];
@@ -514,9 +514,15 @@ __global__ __launch_bounds__(BK_THREADS) void k_bucket(Params p, BatchArgs ba)
     for (int s2 = 0; s2 < MAXHI; ++s2)
 #pragma unroll
         for (int w = 0; w < W; ++w) hm[s2][w] = cb->himask[s2][w];
-    // blocks of hi beyond the first MAXHI (tested from bmL)
+    // block indices of the first MAXHI blocks of hi; blocks beyond them
+    // (hi_rest) are tested from bmL
+    int hb[MAXHI];
     uint64_t hi_rest = hi;
-    for (int s2 = 0; s2 < MAXHI && hi_rest; ++s2) hi_rest &= hi_rest - 1;
+#pragma unroll
+    for (int s2 = 0; s2 < MAXHI; ++s2) {
+        hb[s2] = hi_rest ? __builtin_ctzll(hi_rest) : 0;
+        if (hi_rest) hi_rest &= hi_rest - 1;
+    }
     for (int e = threadIdx.x; e < p.k * W; e += BK_THREADS) bmL[e] = p.bm[(e / W) * MAXW + (e % W)];
     for (int e = threadIdx.x; e < BINS; e += BK_THREADS) hist[e] = 0;
     if (threadIdx.x == 0) ocnt = 0;
@@ -592,13 +598,19 @@ __global__ __launch_bounds__(BK_THREADS) void k_bucket(Params p, BatchArgs ba)
         }
         // Strings of the bucket's points, requested now and used after the
         // histogram and the run claims, which hide the load latency.
+        // Batches of slots at or above m are empty for every thread; the
+        // uniform tests on b * BK_THREADS < m skip them with scalar branches.
         uint64_t sreg[BK_MAXB][W];
 #pragma unroll
         for (int b = 0; b < BK_MAXB; ++b) {
             const int pos = threadIdx.x + b * BK_THREADS;
-            const uint64_t idx = pos < m ? (uint32_t)cur[b] : 0u;
 #pragma unroll
-            for (int w = 0; w < W; ++w) sreg[b][w] = pos < m ? p.S[idx * W + w] : 0ull;
+            for (int w = 0; w < W; ++w) sreg[b][w] = 0ull;
+            if (b * BK_THREADS < m && pos < m) {
+                const uint64_t idx = (uint32_t)cur[b];
+#pragma unroll
+                for (int w = 0; w < W; ++w) sreg[b][w] = p.S[idx * W + w];
+            }
         }
 
         // histogram of the in-bucket digit; the returned count is the rank
@@ -607,7 +619,8 @@ __global__ __launch_bounds__(BK_THREADS) void k_bucket(Params p, BatchArgs ba)
         for (int b = 0; b < BK_MAXB; ++b) {
             const int pos = threadIdx.x + b * BK_THREADS;
             dig[b] = (uint32_t)(cur[b] >> dsh) & (BINS - 1);
-            rank[b] = pos < m ? atomicAdd(&hist[dig[b]], 1u) : 0xFFFFFFFFu;
+            rank[b] = 0xFFFFFFFFu;
+            if (b * BK_THREADS < m && pos < m) rank[b] = atomicAdd(&hist[dig[b]], 1u);
         }
         __syncthreads();
 
@@ -615,48 +628,72 @@ __global__ __launch_bounds__(BK_THREADS) void k_bucket(Params p, BatchArgs ba)
         uint32_t c[BK_MAXB];
 #pragma unroll
         for (int b = 0; b < BK_MAXB; ++b) {
+            c[b] = 0u;
+            if (b * BK_THREADS >= m) continue;
             c[b] = rank[b] != 0xFFFFFFFFu ? hist[dig[b]] : 0u;
-            if (rank[b] == 0 && c[b] >= 2) {
+        }
+        __syncthreads();  // every count is read before the claims reuse hist
+#pragma unroll
+        for (int b = 0; b < BK_MAXB; ++b) {
+            if (b * BK_THREADS < m && rank[b] == 0 && c[b] >= 2) {
                 const unsigned long long old = atomicAdd(&claimRun, (1ull << 32) | (unsigned long long)c[b]);
                 const uint32_t r = (uint32_t)(old >> 32);
                 const uint32_t ms = (uint32_t)old;
-                binStart[dig[b]] = (uint16_t)ms;
-                binRun[dig[b]] = (uint16_t)r;
+                hist[dig[b]] = ms | (r << 16);
                 runS[r] = (uint16_t)ms;
                 runL[r] = (uint16_t)c[b];
-#pragma unroll
-                for (int w = 0; w < W; ++w) runVar[r * W + w] = 0ull;
+                runBlk[r] = 0ull;
             }
         }
         __syncthreads();
 
         // scatter run members and gather their strings
+        uint32_t rfirst[BK_MAXB], rrun[BK_MAXB];
 #pragma unroll
         for (int b = 0; b < BK_MAXB; ++b) {
-            if (c[b] >= 2) {
-                const uint32_t q = binStart[dig[b]] + rank[b];
-                keysB[q] = cur[b];
+            rfirst[b] = 0u;
+            rrun[b] = 0u;
+            if (b * BK_THREADS < m && c[b] >= 2) {
+                const uint32_t packed = hist[dig[b]];
+                rfirst[b] = packed & 0xFFFFu;
+                rrun[b] = packed >> 16;
+                const uint32_t q = rfirst[b] + rank[b];
+                idxB[q] = (uint32_t)cur[b];
 #pragma unroll
                 for (int w = 0; w < W; ++w) sl[q * W + w] = sreg[b][w];
             }
         }
         const uint32_t nruns = (uint32_t)(claimRun >> 32);
         __syncthreads();
-        // Each member ORs its difference from the run's first member into
-        // the run's mask of varying bits; the histogram is cleared for the
-        // next bucket.
+        // Each member marks the blocks of hi in which it differs from the
+        // run's first member; the histogram is cleared for the next bucket.
 #pragma unroll
         for (int b = 0; b < BK_MAXB; ++b) {
-            if (rank[b] != 0xFFFFFFFFu) {
+            if (b * BK_THREADS < m && rank[b] != 0xFFFFFFFFu) {
                 if (hi && c[b] >= 2 && rank[b] > 0) {
-                    const uint32_t first = binStart[dig[b]];
+                    const uint32_t first = rfirst[b];
                     const uint32_t q = first + rank[b];
-                    const uint32_t r = binRun[dig[b]];
+                    uint64_t x[W];
 #pragma unroll
-                    for (int w = 0; w < W; ++w) {
-                        const uint64_t x = sl[q * W + w] ^ sl[first * W + w];
-                        if (x) atomicOr(&runVar[r * W + w], (unsigned long long)x);
+                    for (int w = 0; w < W; ++w) x[w] = sl[q * W + w] ^ sl[first * W + w];
+                    uint64_t bits = 0;
+#pragma unroll
+                    for (int s2 = 0; s2 < MAXHI; ++s2) {
+                        uint64_t any = 0;
+#pragma unroll
+                        for (int w = 0; w < W; ++w) any |= x[w] & hm[s2][w];
+                        bits |= (s2 < nhi && any) ? (1ull << hb[s2]) : 0ull;
                     }
+                    uint64_t need = hi_rest;
+                    while (need) {
+                        const int blk = __builtin_ctzll(need);
+                        need &= need - 1;
+                        uint64_t any = 0;
+#pragma unroll
+                        for (int w = 0; w < W; ++w) any |= x[w] & bmL[blk * W + w];
+                        bits |= any ? (1ull << blk) : 0ull;
+                    }
+                    if (bits) atomicOr(&runBlk[rrun[b]], (unsigned long long)bits);
                 }
                 hist[dig[b]] = 0;
             }
@@ -669,16 +706,7 @@ __global__ __launch_bounds__(BK_THREADS) void k_bucket(Params p, BatchArgs ba)
         // block of `hi` that is constant over the whole run rules it out.
         for (uint32_t r = threadIdx.x; r < nruns; r += BK_THREADS) {
             const int s0 = runS[r], L = runL[r];
-            bool live = true;
-            uint64_t need = hi;
-            while (live && need) {
-                const int blk = __builtin_ctzll(need);
-                need &= need - 1;
-                uint64_t any = 0;
-#pragma unroll
-                for (int w = 0; w < W; ++w) any |= runVar[r * W + w] & p.valid[w] & bmL[blk * W + w];
-                live = any != 0;
-            }
+            const bool live = (runBlk[r] & hi) == hi;
             if (live) {
                 const unsigned long long old =
                     atomicAdd(&claimPair, (1ull << 32) | (unsigned long long)(L * (L - 1) / 2));
@@ -696,8 +724,11 @@ __global__ __launch_bounds__(BK_THREADS) void k_bucket(Params p, BatchArgs ba)
         // Flat loop over all claimed pairs (a < b), row-major per run; each
         // lane tests BK_PAIR_CHUNK consecutive pairs, keeps the results in a
         // bit mask and appends the passing ones once per chunk.
-        for (uint32_t t0 = 0; t0 < P; t0 += BK_THREADS * BK_PAIR_CHUNK) {
-            const uint32_t t = t0 + threadIdx.x * BK_PAIR_CHUNK;
+        // pairs per lane: as few as spread P over the workgroup, at most
+        // BK_PAIR_CHUNK (uniform, so the unrolled loops below stop early)
+        const int cpl = (int)min((uint32_t)BK_PAIR_CHUNK, (P + BK_THREADS - 1) / BK_THREADS);
+        for (uint32_t t0 = 0; t0 < P; t0 += BK_THREADS * (uint32_t)cpl) {
+            const uint32_t t = t0 + threadIdx.x * (uint32_t)cpl;
             int r = 0, a = 0, bb = 1, L = 2, s0 = 0;
             if (t < P) {
                 int lo = 0, hi2 = (int)nlive;
@@ -724,6 +755,7 @@ __global__ __launch_bounds__(BK_THREADS) void k_bucket(Params p, BatchArgs ba)
             int pa[BK_PAIR_CHUNK], pb[BK_PAIR_CHUNK];
 #pragma unroll
             for (int q = 0; q < BK_PAIR_CHUNK; ++q) {
+                if (q >= cpl) break;
                 pa[q] = min(s0 + a, BK_CAP - 1);
                 pb[q] = min(s0 + bb, BK_CAP - 1);
                 ++bb;
@@ -743,18 +775,19 @@ __global__ __launch_bounds__(BK_THREADS) void k_bucket(Params p, BatchArgs ba)
             uint32_t pi[BK_PAIR_CHUNK], pj[BK_PAIR_CHUNK];
 #pragma unroll
             for (int q = 0; q < BK_PAIR_CHUNK; ++q) {
+                if (q >= cpl) break;
                 const bool live = t + q < P;
-                const uint64_t ka = keysB[pa[q]], kb = keysB[pb[q]];
-                pi[q] = (uint32_t)ka;
-                pj[q] = (uint32_t)kb;
-                const bool ok = live & ((ka >> 32) == (kb >> 32)) &
-                                pair_ok_fast<W>(&sl[pa[q] * W], &sl[pb[q] * W], p, keep, hm, nhi, hi_rest, bmL);
+                pi[q] = idxB[pa[q]];
+                pj[q] = idxB[pb[q]];
+                const bool ok = live & pair_ok_fast<W>(&sl[pa[q] * W], &sl[pb[q] * W], p, keep, hm, nhi, hi_rest, bmL);
                 okbits |= (uint32_t)ok << q;
             }
             if (p.rep > 0 && okbits) {
 #pragma unroll
-                for (int q = 0; q < BK_PAIR_CHUNK; ++q)
+                for (int q = 0; q < BK_PAIR_CHUNK; ++q) {
+                    if (q >= cpl) break;
                     if (((okbits >> q) & 1u) && !far_in_earlier<W>(p, pi[q], pj[q])) okbits &= ~(1u << q);
+                }
             }
             // one append per lane per chunk: wave prefix of the counts, one
             // LDS atomic per wave
@@ -778,6 +811,7 @@ __global__ __launch_bounds__(BK_THREADS) void k_bucket(Params p, BatchArgs ba)
             }
 #pragma unroll
             for (int q = 0; q < BK_PAIR_CHUNK; ++q) {
+                if (q >= cpl) break;
                 if ((okbits >> q) & 1u) {
                     const uint32_t lo2 = (pi[q] < pj[q] ? pi[q] : pj[q]) - o_off;
                     const uint32_t hi3 = (pi[q] < pj[q] ? pj[q] : pi[q]) - o_off;
@@ -790,7 +824,7 @@ __global__ __launch_bounds__(BK_THREADS) void k_bucket(Params p, BatchArgs ba)
                     ++slot;
                 }
             }
-            if (t0 + BK_THREADS * BK_PAIR_CHUNK < P) out.maybe_flush(BK_OUT / 2);
+            if (t0 + BK_THREADS * (uint32_t)cpl < P) out.maybe_flush(BK_OUT / 2);
         }
         out.maybe_flush(BK_OUT / 2);
     }
