@@ -360,7 +360,10 @@ def run_learned(args):
     tp, tl, stats = L.mine_pairs(ctx, Xt, w.eps, n_pos=200_000, n_neg=200_000, seed=w.seed_sub + 8)
     torch.cuda.synchronize()
     t_mine = time.perf_counter() - t0
-    cfg = L.TrainConfig(hid=512, ell=w.ell, h=w.h, lam=0.05, lr=1e-3, batch=4096, epochs=args.epochs, seed=11)
+    # the loss's h is twice the MSM threshold: epsilon-pairs are pulled to
+    # Hamming distance h_MSM, other pairs pushed beyond 6 h_MSM
+    cfg = L.TrainConfig(hid=512, ell=w.ell, h=args.train_h or 2 * w.h, lam=0.05, lr=1e-3, batch=4096,
+                        epochs=args.epochs, seed=11)
     t0 = time.perf_counter()
     params, _, _, losses, nsteps = L.train(ctx, Xt, tp, tl, cfg, I.mlp_initial_parameters(w.d, cfg.hid, w.ell, 12))
     torch.cuda.synchronize()
@@ -571,7 +574,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-second-reading", action="store_true",
                     help="skip the run under the other reading of sigma")
-    ap.add_argument("--epochs", type=int, default=10, help="training epochs of the learned form")
+    ap.add_argument("--epochs", type=int, default=20, help="training epochs of the learned form")
+    ap.add_argument("--train-h", type=int, default=0,
+                    help="h of the training loss of the learned form (0: twice the workload's h)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES on the device a few times (reference for the HBM counters)")
     ap.add_argument("--workload", default="paper", choices=["paper", "precision", "learned", "batched", "sweep"],

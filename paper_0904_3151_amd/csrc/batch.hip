@@ -67,6 +67,7 @@ struct msm_batch {
     uint32_t* d_counts = nullptr;
     uint32_t* d_base = nullptr;
     Ovf* d_ovf = nullptr;
+    Ovf* d_ovf2 = nullptr;
     uint32_t* d_ovfc = nullptr;
     uint64_t* d_tile0 = nullptr;
     unsigned long long* d_work = nullptr;
@@ -165,8 +166,8 @@ msm_status set_config(msm_batch& b, const Config& c)
 template <int W, int DIGIT>
 void launch_bucket(const Params& p, const BatchArgs& ba, int NB, int cc, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_bucket<W, DIGIT, true>), dim3((NB + ba.group - 1) / ba.group, cc), dim3(BK_THREADS), 0, s,
-                       p, ba);
+    hipLaunchKernelGGL((k_bucket<W, DIGIT, true, BK_THREADS, false, BK_MAXB>), dim3((NB + ba.group - 1) / ba.group, cc),
+                       dim3(BK_THREADS), 0, s, p, ba);
 }
 
 template <int W>
@@ -195,7 +196,6 @@ msm_status enqueue_enumerate(msm_batch& b, int64_t* m_dev, hipStream_t s, bool t
     for (int w = 0; w < MAXW; ++w) p.valid[w] = b.valid[w];
     p.r1 = 0;
     p.nb = b.NB;
-    p.sort_lo = 0;
     p.T = BATCH_T;
     p.nt = b.nt;
     p.counts = b.d_counts;
@@ -206,6 +206,10 @@ msm_status enqueue_enumerate(msm_batch& b, int64_t* m_dev, hipStream_t s, bool t
     p.counter = nullptr;
     p.ovf = b.d_ovf;
     p.ovf_count = b.d_ovfc;
+    p.list = b.d_ovf;
+    p.list_count = b.d_ovfc;
+    p.ovf2 = b.d_ovf2;
+    p.ovf2_count = b.d_ovfc + 1;
     BatchArgs ba{b.d_inst, b.d_tile_inst, b.d_bucket_inst, b.cnt_stride, b.cfg.group,
                  reinterpret_cast<unsigned long long*>(m_dev)};
     const int big_grid = 2 * ctx->num_cu;
@@ -233,10 +237,18 @@ msm_status enqueue_enumerate(msm_batch& b, int64_t* m_dev, hipStream_t s, bool t
             if (prof) kt.reset(new msm::KernelTimer(ctx, s, "k_bucket_batch"));
             launch_bucket_digit<W>(p, ba, b.cfg.digit, b.NB, cc, s);
             kt.reset();
-            if (prof) kt.reset(new msm::KernelTimer(ctx, s, "k_big_batch"));
+            // buckets above the first pass's capacity: a persistent second
+            // pass with more threads and LDS, then tile pairs for the rest
             const uint32_t ovf_cap = (uint32_t)cc * (uint32_t)b.NB;
-            hipLaunchKernelGGL(k_ovf_prefix, dim3(1), dim3(1024), 0, s, b.d_ovf, b.d_ovfc, ovf_cap, b.d_tile0);
-            hipLaunchKernelGGL((k_big_batch<W>), dim3(big_grid), dim3(BIG_TILE), 0, s, p, ba, b.d_ovf, b.d_ovfc,
+            p.list_cap = ovf_cap;
+            if (prof) kt.reset(new msm::KernelTimer(ctx, s, "k_bucket_large_batch"));
+            hipLaunchKernelGGL((k_bucket<W, BK_DIGIT_L, true, LARGE_THREADS, true, large_maxb<W>()>),
+                               dim3((unsigned)std::min<uint32_t>(ovf_cap, (uint32_t)big_grid)),
+                               dim3(LARGE_THREADS), 0, s, p, ba);
+            kt.reset();
+            if (prof) kt.reset(new msm::KernelTimer(ctx, s, "k_big_batch"));
+            hipLaunchKernelGGL(k_ovf_prefix, dim3(1), dim3(1024), 0, s, b.d_ovf2, b.d_ovfc + 1, ovf_cap, b.d_tile0);
+            hipLaunchKernelGGL((k_big_batch<W>), dim3(big_grid), dim3(BIG_TILE), 0, s, p, ba, b.d_ovf2, b.d_ovfc + 1,
                                ovf_cap, b.d_tile0, b.d_work);
         }
         MSM_HIP(ctx, hipGetLastError());
@@ -398,7 +410,7 @@ extern "C" msm_status msm_batch_create(msm_ctx* ctx, const msm_instance* inst, i
     const Sizes zs = sizes_for(*b, autotune_flag ? 256 : 512);
     const size_t per_combo = msm::align_up((size_t)N * 8, 256) + msm::align_up(zs.cnt_stride * 4, 256) +
                              msm::align_up((size_t)(zs.NB + 1) * 4, 256) +
-                             msm::align_up((size_t)zs.NB * sizeof(Ovf), 256) +
+                             2 * msm::align_up((size_t)zs.NB * sizeof(Ovf), 256) +
                              msm::align_up((size_t)(zs.NB + 1) * 8, 256);
     const size_t budget = (size_t)3 << 30;
     b->Cg = (int)std::max<size_t>(1, std::min<size_t>((size_t)b->C, budget / std::max<size_t>(per_combo, 1)));
@@ -416,6 +428,7 @@ extern "C" msm_status msm_batch_create(msm_ctx* ctx, const msm_instance* inst, i
     cv.take<uint64_t>(std::max<size_t>(1, (size_t)Cg * N));
     cv.take<uint32_t>(std::max<size_t>(1, (size_t)Cg * zs.cnt_stride));
     cv.take<uint32_t>((size_t)Cg * (zs.NB + 1));
+    cv.take<Ovf>((size_t)Cg * zs.NB);
     cv.take<Ovf>((size_t)Cg * zs.NB);
     cv.take<uint32_t>(4);
     cv.take<uint64_t>((size_t)Cg * zs.NB + 1);
@@ -442,6 +455,7 @@ extern "C" msm_status msm_batch_create(msm_ctx* ctx, const msm_instance* inst, i
     b->d_counts = c2.take<uint32_t>(std::max<size_t>(1, (size_t)Cg * zs.cnt_stride));
     b->d_base = c2.take<uint32_t>((size_t)Cg * (zs.NB + 1));
     b->d_ovf = c2.take<Ovf>((size_t)Cg * zs.NB);
+    b->d_ovf2 = c2.take<Ovf>((size_t)Cg * zs.NB);
     b->d_ovfc = c2.take<uint32_t>(4);
     b->d_tile0 = c2.take<uint64_t>((size_t)Cg * zs.NB + 1);
     b->d_work = c2.take<unsigned long long>(1);

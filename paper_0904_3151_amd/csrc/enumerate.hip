@@ -19,14 +19,13 @@ msm_status run_enumerate(msm_ctx* ctx, const uint64_t* S, int64_t n, int ell, in
     int r1 = 0;
     while (r1 < 13 && ((int64_t)1 << r1) * TARGET_BUCKET < n) ++r1;
     const int nb = 1 << r1;
-    const int sort_lo = 32 - r1 - BK_DIGIT;
     int T = 4096;  // points per partition tile; at most 256 tiles per combination
     while ((n + T - 1) / T > 256) T *= 2;
     const int nt = (int)((n + T - 1) / T);
 
     // Combinations per launch group, bounded by scratch size.
     const size_t per_combo = msm::align_up((size_t)n * 8, 256) + msm::align_up((size_t)nt * nb * 4, 256) +
-                             msm::align_up((size_t)(nb + 1) * 4, 256) + msm::align_up((size_t)nb * sizeof(Ovf), 256);
+                             msm::align_up((size_t)(nb + 1) * 4, 256) + 2 * msm::align_up((size_t)nb * sizeof(Ovf), 256);
     const size_t budget = (size_t)3 << 30;
     int Cg = (int)std::max<size_t>(1, std::min<size_t>((size_t)C, budget / per_combo));
     Cg = std::min(Cg, 65535);
@@ -39,6 +38,7 @@ msm_status run_enumerate(msm_ctx* ctx, const uint64_t* S, int64_t n, int ell, in
     cv.take<uint64_t>((size_t)Cg * n);
     cv.take<uint32_t>((size_t)Cg * nt * nb);
     cv.take<uint32_t>((size_t)Cg * (nb + 1));
+    cv.take<Ovf>((size_t)Cg * nb);
     cv.take<Ovf>((size_t)Cg * nb);
     cv.take<uint64_t>((size_t)Cg * nb + 1);
     void* scr = nullptr;
@@ -54,6 +54,7 @@ msm_status run_enumerate(msm_ctx* ctx, const uint64_t* S, int64_t n, int ell, in
     uint32_t* d_counts = c2.take<uint32_t>((size_t)Cg * nt * nb);
     uint32_t* d_base = c2.take<uint32_t>((size_t)Cg * (nb + 1));
     Ovf* d_ovf = c2.take<Ovf>((size_t)Cg * nb);
+    Ovf* d_ovf2 = c2.take<Ovf>((size_t)Cg * nb);
     uint64_t* d_tile0 = c2.take<uint64_t>((size_t)Cg * nb + 1);
 
     MSM_HIP(ctx, hipMemcpyAsync(d_combos, combos.data(), sizeof(Combo) * C, hipMemcpyHostToDevice, stream));
@@ -72,7 +73,6 @@ msm_status run_enumerate(msm_ctx* ctx, const uint64_t* S, int64_t n, int ell, in
     for (int w = 0; w < MAXW; ++w) p.valid[w] = valid[w];
     p.r1 = r1;
     p.nb = nb;
-    p.sort_lo = sort_lo;
     p.T = T;
     p.nt = nt;
     p.counts = d_counts;
@@ -83,6 +83,10 @@ msm_status run_enumerate(msm_ctx* ctx, const uint64_t* S, int64_t n, int ell, in
     p.counter = d_counter;
     p.ovf = d_ovf;
     p.ovf_count = d_ovfc;
+    p.list = d_ovf;
+    p.list_count = d_ovfc;
+    p.ovf2 = d_ovf2;
+    p.ovf2_count = d_ovfc + 1;
 
     std::vector<Ovf> hovf;
     std::vector<uint64_t> htile;
@@ -111,16 +115,32 @@ msm_status run_enumerate(msm_ctx* ctx, const uint64_t* S, int64_t n, int ell, in
         }
         {
             msm::KernelTimer kt(ctx, stream, "k_bucket");
-            hipLaunchKernelGGL((k_bucket<W, BK_DIGIT, false>), dim3((nb + BK_GROUP - 1) / BK_GROUP, cc),
+            hipLaunchKernelGGL((k_bucket<W, BK_DIGIT, false, BK_THREADS, false, BK_MAXB>), dim3((nb + BK_GROUP - 1) / BK_GROUP, cc),
                                dim3(BK_THREADS), 0, stream, p, BatchArgs{});
         }
         MSM_HIP(ctx, hipGetLastError());
         MSM_HIP(ctx, hipMemcpyAsync(ctx->host_words, d_ovfc, sizeof(uint32_t), hipMemcpyDeviceToHost, stream));
         MSM_HIP(ctx, hipStreamSynchronize(stream));
-        const uint32_t novf = *reinterpret_cast<uint32_t*>(ctx->host_words);
+        const uint32_t nlarge = *reinterpret_cast<uint32_t*>(ctx->host_words);
+        uint32_t novf = 0;
+        if (nlarge > 0) {
+            // buckets above the first pass's capacity: a second pass with
+            // more threads and LDS takes those up to its own capacity
+            p.list_cap = (uint32_t)cc * (uint32_t)nb;
+            {
+                msm::KernelTimer kt(ctx, stream, "k_bucket_large");
+                hipLaunchKernelGGL((k_bucket<W, BK_DIGIT_L, false, LARGE_THREADS, true, large_maxb<W>()>), dim3(nlarge),
+                                   dim3(LARGE_THREADS), 0, stream, p, BatchArgs{});
+            }
+            MSM_HIP(ctx, hipGetLastError());
+            MSM_HIP(ctx, hipMemcpyAsync(ctx->host_words, d_ovfc + 1, sizeof(uint32_t), hipMemcpyDeviceToHost,
+                                        stream));
+            MSM_HIP(ctx, hipStreamSynchronize(stream));
+            novf = *reinterpret_cast<uint32_t*>(ctx->host_words);
+        }
         if (novf > 0) {
             hovf.resize(novf);
-            MSM_HIP(ctx, hipMemcpy(hovf.data(), d_ovf, sizeof(Ovf) * novf, hipMemcpyDeviceToHost));
+            MSM_HIP(ctx, hipMemcpy(hovf.data(), d_ovf2, sizeof(Ovf) * novf, hipMemcpyDeviceToHost));
             htile.assign(novf + 1, 0);
             for (uint32_t o = 0; o < novf; ++o) {
                 const uint64_t t = (hovf[o].m + BIG_TILE - 1) / BIG_TILE;
@@ -134,7 +154,7 @@ msm_status run_enumerate(msm_ctx* ctx, const uint64_t* S, int64_t n, int ell, in
             MSM_HIP(ctx, hipMemcpyAsync(d_tile0, htile.data(), sizeof(uint64_t) * (novf + 1),
                                         hipMemcpyHostToDevice, stream));
             msm::KernelTimer kt(ctx, stream, "k_big");
-            hipLaunchKernelGGL((k_big<W>), dim3((unsigned)tiles), dim3(BIG_TILE), 0, stream, p, d_ovf,
+            hipLaunchKernelGGL((k_big<W>), dim3((unsigned)tiles), dim3(BIG_TILE), 0, stream, p, d_ovf2,
                                d_tile0, (int)novf);
             MSM_HIP(ctx, hipGetLastError());
         }

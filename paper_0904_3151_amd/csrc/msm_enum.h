@@ -56,12 +56,22 @@ constexpr int BK_PAIR_CHUNK = 8;                  // consecutive pairs per lane
 constexpr int BK_GROUP = 8;                       // buckets per workgroup
 constexpr int BK_OUT = 512;                       // staged output pairs per workgroup
 constexpr int BK_DIGIT = 10;                      // mix bits counted inside a bucket
+constexpr int BK_DIGIT_L = 12;                    // the same in the second pass over large buckets
 constexpr int BK_BINS = 1 << BK_DIGIT;
 constexpr int BIG_TILE = 256;
 constexpr int MAX_BUCKETS = 8192;
 constexpr int TARGET_BUCKET = 512;
 
 constexpr int MAXHI = 4;   // blocks of `hi` tested from unrolled masks
+
+// Threads and points per thread of the second bucket pass, sized so that
+// its LDS stays below 160 KB (capacity 4096 points for W <= 2, else 2048).
+constexpr int LARGE_THREADS = 512;
+template <int W>
+constexpr int large_maxb()
+{
+    return W <= 2 ? 8 : 4;
+}
 
 struct Combo {                    // one set B of masked blocks
     uint64_t keep[MAXW];          // characters below ell outside the blocks of B
@@ -89,7 +99,6 @@ struct Params {
     uint64_t valid[MAXW];    // bits below ell
     int r1;                  // bucket bits (top bits of the mix)
     int nb;                  // 1 << r1
-    int sort_lo;             // runs share mix >> sort_lo
     int T, nt;               // partition tile size and count
     int units;               // combinations of the group x tiles
     uint32_t* counts;        // [c][t][b] tile counts, then tile offsets
@@ -100,6 +109,12 @@ struct Params {
     unsigned long long* counter;
     Ovf* ovf;
     uint32_t* ovf_count;
+    // second pass over the overflow list (k_bucket with LIST)
+    const Ovf* list;
+    const uint32_t* list_count;
+    uint32_t list_cap;
+    Ovf* ovf2;
+    uint32_t* ovf2_count;
 };
 
 // Batched enumeration over many independent instances at once: their
@@ -481,21 +496,29 @@ __device__ __forceinline__ bool far_in_earlier(const Params& p, uint32_t i, uint
 // and a flat loop over the claimed pairs tests them. Bins that mix several
 // masked strings only add candidates, which the exact test rejects.
 
-template <int W, int DIGIT, bool BATCH>
-__global__ __launch_bounds__(BK_THREADS) void k_bucket(Params p, BatchArgs ba)
+// TH threads take buckets of up to TH * MAXB points. Without LIST a
+// workgroup takes `group` consecutive buckets of combination blockIdx.y;
+// with LIST it takes entries of an overflow list (buckets another pass
+// found too large), and lists the ones too large for it in p.ovf2.
+// The first pass for W <= 2 fits four workgroups per CU in LDS; its
+// register budget is held to the matching four waves per SIMD.
+template <int W, int DIGIT, bool BATCH, int TH, bool LIST, int MAXB>
+__global__ __launch_bounds__(TH, (TH == BK_THREADS && W <= 2 && DIGIT <= 10) ? 4 : 1) void k_bucket(Params p,
+                                                                                                   BatchArgs ba)
 {
     constexpr int BINS = 1 << DIGIT;
+    constexpr int CAP = TH * MAXB;
     // hist holds the digit counts, then (for bins that form runs) the run's
     // first slot in the member arrays | run index << 16
     __shared__ uint32_t hist[BINS];
-    __shared__ uint32_t idxB[BK_CAP];
-    __shared__ uint64_t sl[BK_CAP * W];
-    __shared__ uint16_t runS[BK_CAP / 2];
-    __shared__ uint16_t runL[BK_CAP / 2];
-    __shared__ unsigned long long runBlk[BK_CAP / 2];  // blocks of hi that vary inside the run
-    __shared__ uint16_t liveS[BK_CAP / 2];
-    __shared__ uint16_t liveL[BK_CAP / 2];
-    __shared__ uint32_t liveP[BK_CAP / 2];
+    __shared__ uint32_t idxB[CAP];
+    __shared__ uint64_t sl[CAP * W];
+    __shared__ uint16_t runS[CAP / 2];
+    __shared__ uint16_t runL[CAP / 2];
+    __shared__ unsigned long long runBlk[CAP / 2];  // blocks of hi that vary inside the run
+    __shared__ uint16_t liveS[CAP / 2];
+    __shared__ uint16_t liveL[CAP / 2];
+    __shared__ uint32_t liveP[CAP / 2];
     __shared__ uint64_t bmL[MAXK * W];
     __shared__ unsigned long long claimRun;   // runs << 32 | members
     __shared__ unsigned long long claimPair;  // live runs << 32 | pairs
@@ -503,28 +526,38 @@ __global__ __launch_bounds__(BK_THREADS) void k_bucket(Params p, BatchArgs ba)
     __shared__ uint32_t ocnt;
     __shared__ unsigned long long ogb;
 
-    const int cl = blockIdx.y;
-    const Combo* cb = p.combos + cl;
+    // the combination's masks in registers; hb holds the block indices of
+    // the first MAXHI blocks of hi, blocks beyond them (hi_rest) are tested
+    // from bmL
+    int cl = -1;
     uint64_t keep[W];
-    load_keep<W>(cb, keep);
-    const uint64_t hi = cb->hi;
-    const int nhi = cb->nhi;
+    uint64_t hi = 0;
+    int nhi = 0;
     uint64_t hm[MAXHI][W];
-#pragma unroll
-    for (int s2 = 0; s2 < MAXHI; ++s2)
-#pragma unroll
-        for (int w = 0; w < W; ++w) hm[s2][w] = cb->himask[s2][w];
-    // block indices of the first MAXHI blocks of hi; blocks beyond them
-    // (hi_rest) are tested from bmL
     int hb[MAXHI];
-    uint64_t hi_rest = hi;
+    uint64_t hi_rest = 0;
+    auto load_combo = [&](int c) {
+        const Combo* cb = p.combos + c;
+        load_keep<W>(cb, keep);
+        hi = cb->hi;
+        nhi = cb->nhi;
 #pragma unroll
-    for (int s2 = 0; s2 < MAXHI; ++s2) {
-        hb[s2] = hi_rest ? __builtin_ctzll(hi_rest) : 0;
-        if (hi_rest) hi_rest &= hi_rest - 1;
+        for (int s2 = 0; s2 < MAXHI; ++s2)
+#pragma unroll
+            for (int w = 0; w < W; ++w) hm[s2][w] = cb->himask[s2][w];
+        hi_rest = hi;
+#pragma unroll
+        for (int s2 = 0; s2 < MAXHI; ++s2) {
+            hb[s2] = hi_rest ? __builtin_ctzll(hi_rest) : 0;
+            if (hi_rest) hi_rest &= hi_rest - 1;
+        }
+    };
+    if (!LIST) {
+        cl = (int)blockIdx.y;
+        load_combo(cl);
     }
-    for (int e = threadIdx.x; e < p.k * W; e += BK_THREADS) bmL[e] = p.bm[(e / W) * MAXW + (e % W)];
-    for (int e = threadIdx.x; e < BINS; e += BK_THREADS) hist[e] = 0;
+    for (int e = threadIdx.x; e < p.k * W; e += TH) bmL[e] = p.bm[(e / W) * MAXW + (e % W)];
+    for (int e = threadIdx.x; e < BINS; e += TH) hist[e] = 0;
     if (threadIdx.x == 0) ocnt = 0;
     // output destination; in a batch it follows the instance of the bucket
     uint32_t* o_pairs = p.pairs;
@@ -533,29 +566,67 @@ __global__ __launch_bounds__(BK_THREADS) void k_bucket(Params p, BatchArgs ba)
     uint32_t o_off = 0;
     uint32_t cur_inst = 0xFFFFFFFFu;
     msm::PairStager<BK_OUT> out{obuf, &ocnt, &ogb, o_pairs, o_cap, o_counter};
-    const uint32_t* base = p.base + (size_t)cl * (p.nb + 1);
-    const uint64_t* part = p.part + (size_t)cl * p.n;
+    const uint32_t* base = LIST ? nullptr : p.base + (size_t)cl * (p.nb + 1);
+    const uint64_t* part = LIST ? p.part : p.part + (size_t)cl * p.n;
     const int group = BATCH ? ba.group : BK_GROUP;
-    const int bk0 = blockIdx.x * group;
-    const int bk1 = min(p.nb, bk0 + group);
-    int dsh = 32 + p.sort_lo;
+    const int bk0 = LIST ? 0 : (int)blockIdx.x * group;
+    const int bk1 = LIST ? 0 : min(p.nb, bk0 + group);
+    const uint32_t nlist = LIST ? min(*p.list_count, p.list_cap) : 0u;
+    int dsh = 64 - p.r1 - DIGIT;
 
     // keys of the current bucket, loaded one bucket ahead
-    uint64_t key[BK_MAXB];
-    uint32_t nbeg = base[bk0];
-    uint32_t ncnt = base[bk0 + 1] - nbeg;
+    uint64_t key[MAXB];
+    uint32_t nbeg = 0, ncnt = 0;
+    if (!LIST) {
+        nbeg = base[bk0];
+        ncnt = base[bk0 + 1] - nbeg;
 #pragma unroll
-    for (int b = 0; b < BK_MAXB; ++b) {
-        const int pos = threadIdx.x + b * BK_THREADS;
-        key[b] = (ncnt <= (uint32_t)BK_CAP && pos < (int)ncnt) ? part[nbeg + pos] : ~0ull;
+        for (int b = 0; b < MAXB; ++b) {
+            const int pos = threadIdx.x + b * TH;
+            key[b] = (ncnt <= (uint32_t)CAP && pos < (int)ncnt) ? part[nbeg + pos] : ~0ull;
+        }
     }
 
-    for (int bk = bk0; bk < bk1; ++bk) {
-        const uint32_t beg = nbeg;
-        const uint32_t cnt = ncnt;
+    for (int it = 0;; ++it) {
+        uint32_t beg, cnt;
         uint32_t inst_id = 0;
+        uint64_t cur[MAXB];
+        if (LIST) {
+            const uint32_t li = blockIdx.x + (uint32_t)it * gridDim.x;
+            if (li >= nlist) break;
+            const Ovf e = p.list[li];
+            if ((int)e.c != cl) {
+                cl = (int)e.c;
+                load_combo(cl);
+                part = p.part + (size_t)cl * p.n;
+            }
+            beg = e.beg;
+            cnt = e.m;
+            inst_id = e.pad;
+#pragma unroll
+            for (int b = 0; b < MAXB; ++b) {
+                const int pos = threadIdx.x + b * TH;
+                cur[b] = (cnt <= (uint32_t)CAP && pos < (int)cnt) ? part[beg + pos] : ~0ull;
+            }
+        } else {
+            const int bk = bk0 + it;
+            if (bk >= bk1) break;
+            beg = nbeg;
+            cnt = ncnt;
+#pragma unroll
+            for (int b = 0; b < MAXB; ++b) cur[b] = key[b];
+            if (bk + 1 < bk1) {
+                nbeg = base[bk + 1];
+                ncnt = base[bk + 2] - nbeg;
+#pragma unroll
+                for (int b = 0; b < MAXB; ++b) {
+                    const int pos = threadIdx.x + b * TH;
+                    key[b] = (ncnt <= (uint32_t)CAP && pos < (int)ncnt) ? part[nbeg + pos] : ~0ull;
+                }
+            }
+            if (BATCH) inst_id = ba.bucket_inst[bk];
+        }
         if (BATCH) {
-            inst_id = ba.bucket_inst[bk];
             const int r = ba.inst[inst_id].r;
             dsh = 64 - r - DIGIT;
             if (inst_id != cur_inst) {
@@ -570,24 +641,17 @@ __global__ __launch_bounds__(BK_THREADS) void k_bucket(Params p, BatchArgs ba)
                 out.counter = o_counter;
             }
         }
-        uint64_t cur[BK_MAXB];
-#pragma unroll
-        for (int b = 0; b < BK_MAXB; ++b) cur[b] = key[b];
-        if (bk + 1 < bk1) {
-            nbeg = base[bk + 1];
-            ncnt = base[bk + 2] - nbeg;
-#pragma unroll
-            for (int b = 0; b < BK_MAXB; ++b) {
-                const int pos = threadIdx.x + b * BK_THREADS;
-                key[b] = (ncnt <= (uint32_t)BK_CAP && pos < (int)ncnt) ? part[nbeg + pos] : ~0ull;
-            }
-        }
         __syncthreads();  // LDS of the previous bucket is free, hist is zero
         if (cnt < 2) continue;
-        if (cnt > (uint32_t)BK_CAP) {
+        if (cnt > (uint32_t)CAP) {
             if (threadIdx.x == 0) {
-                const uint32_t o = atomicAdd(p.ovf_count, 1u);
-                p.ovf[o] = Ovf{(uint32_t)cl, beg, cnt, inst_id};
+                if (LIST) {
+                    const uint32_t o = atomicAdd(p.ovf2_count, 1u);
+                    p.ovf2[o] = Ovf{(uint32_t)cl, beg, cnt, inst_id};
+                } else {
+                    const uint32_t o = atomicAdd(p.ovf_count, 1u);
+                    p.ovf[o] = Ovf{(uint32_t)cl, beg, cnt, inst_id};
+                }
             }
             continue;
         }
@@ -599,14 +663,14 @@ __global__ __launch_bounds__(BK_THREADS) void k_bucket(Params p, BatchArgs ba)
         // Strings of the bucket's points, requested now and used after the
         // histogram and the run claims, which hide the load latency.
         // Batches of slots at or above m are empty for every thread; the
-        // uniform tests on b * BK_THREADS < m skip them with scalar branches.
-        uint64_t sreg[BK_MAXB][W];
+        // uniform tests on b * TH < m skip them with scalar branches.
+        uint64_t sreg[MAXB][W];
 #pragma unroll
-        for (int b = 0; b < BK_MAXB; ++b) {
-            const int pos = threadIdx.x + b * BK_THREADS;
+        for (int b = 0; b < MAXB; ++b) {
+            const int pos = threadIdx.x + b * TH;
 #pragma unroll
             for (int w = 0; w < W; ++w) sreg[b][w] = 0ull;
-            if (b * BK_THREADS < m && pos < m) {
+            if (b * TH < m && pos < m) {
                 const uint64_t idx = (uint32_t)cur[b];
 #pragma unroll
                 for (int w = 0; w < W; ++w) sreg[b][w] = p.S[idx * W + w];
@@ -614,28 +678,28 @@ __global__ __launch_bounds__(BK_THREADS) void k_bucket(Params p, BatchArgs ba)
         }
 
         // histogram of the in-bucket digit; the returned count is the rank
-        uint32_t dig[BK_MAXB], rank[BK_MAXB];
+        uint32_t dig[MAXB], rank[MAXB];
 #pragma unroll
-        for (int b = 0; b < BK_MAXB; ++b) {
-            const int pos = threadIdx.x + b * BK_THREADS;
+        for (int b = 0; b < MAXB; ++b) {
+            const int pos = threadIdx.x + b * TH;
             dig[b] = (uint32_t)(cur[b] >> dsh) & (BINS - 1);
             rank[b] = 0xFFFFFFFFu;
-            if (b * BK_THREADS < m && pos < m) rank[b] = atomicAdd(&hist[dig[b]], 1u);
+            if (b * TH < m && pos < m) rank[b] = atomicAdd(&hist[dig[b]], 1u);
         }
         __syncthreads();
 
         // the first member of each run claims the run and its member range
-        uint32_t c[BK_MAXB];
+        uint32_t c[MAXB];
 #pragma unroll
-        for (int b = 0; b < BK_MAXB; ++b) {
+        for (int b = 0; b < MAXB; ++b) {
             c[b] = 0u;
-            if (b * BK_THREADS >= m) continue;
+            if (b * TH >= m) continue;
             c[b] = rank[b] != 0xFFFFFFFFu ? hist[dig[b]] : 0u;
         }
         __syncthreads();  // every count is read before the claims reuse hist
 #pragma unroll
-        for (int b = 0; b < BK_MAXB; ++b) {
-            if (b * BK_THREADS < m && rank[b] == 0 && c[b] >= 2) {
+        for (int b = 0; b < MAXB; ++b) {
+            if (b * TH < m && rank[b] == 0 && c[b] >= 2) {
                 const unsigned long long old = atomicAdd(&claimRun, (1ull << 32) | (unsigned long long)c[b]);
                 const uint32_t r = (uint32_t)(old >> 32);
                 const uint32_t ms = (uint32_t)old;
@@ -648,12 +712,12 @@ __global__ __launch_bounds__(BK_THREADS) void k_bucket(Params p, BatchArgs ba)
         __syncthreads();
 
         // scatter run members and gather their strings
-        uint32_t rfirst[BK_MAXB], rrun[BK_MAXB];
+        uint32_t rfirst[MAXB], rrun[MAXB];
 #pragma unroll
-        for (int b = 0; b < BK_MAXB; ++b) {
+        for (int b = 0; b < MAXB; ++b) {
             rfirst[b] = 0u;
             rrun[b] = 0u;
-            if (b * BK_THREADS < m && c[b] >= 2) {
+            if (b * TH < m && c[b] >= 2) {
                 const uint32_t packed = hist[dig[b]];
                 rfirst[b] = packed & 0xFFFFu;
                 rrun[b] = packed >> 16;
@@ -668,8 +732,8 @@ __global__ __launch_bounds__(BK_THREADS) void k_bucket(Params p, BatchArgs ba)
         // Each member marks the blocks of hi in which it differs from the
         // run's first member; the histogram is cleared for the next bucket.
 #pragma unroll
-        for (int b = 0; b < BK_MAXB; ++b) {
-            if (b * BK_THREADS < m && rank[b] != 0xFFFFFFFFu) {
+        for (int b = 0; b < MAXB; ++b) {
+            if (b * TH < m && rank[b] != 0xFFFFFFFFu) {
                 if (hi && c[b] >= 2 && rank[b] > 0) {
                     const uint32_t first = rfirst[b];
                     const uint32_t q = first + rank[b];
@@ -704,7 +768,7 @@ __global__ __launch_bounds__(BK_THREADS) void k_bucket(Params p, BatchArgs ba)
         // Each run claims its pairs, unless it cannot hold a pair to write:
         // a pair is written only if it differs in every block of `hi`, so a
         // block of `hi` that is constant over the whole run rules it out.
-        for (uint32_t r = threadIdx.x; r < nruns; r += BK_THREADS) {
+        for (uint32_t r = threadIdx.x; r < nruns; r += TH) {
             const int s0 = runS[r], L = runL[r];
             const bool live = (runBlk[r] & hi) == hi;
             if (live) {
@@ -726,8 +790,8 @@ __global__ __launch_bounds__(BK_THREADS) void k_bucket(Params p, BatchArgs ba)
         // bit mask and appends the passing ones once per chunk.
         // pairs per lane: as few as spread P over the workgroup, at most
         // BK_PAIR_CHUNK (uniform, so the unrolled loops below stop early)
-        const int cpl = (int)min((uint32_t)BK_PAIR_CHUNK, (P + BK_THREADS - 1) / BK_THREADS);
-        for (uint32_t t0 = 0; t0 < P; t0 += BK_THREADS * (uint32_t)cpl) {
+        const int cpl = (int)min((uint32_t)BK_PAIR_CHUNK, (P + TH - 1) / TH);
+        for (uint32_t t0 = 0; t0 < P; t0 += TH * (uint32_t)cpl) {
             const uint32_t t = t0 + threadIdx.x * (uint32_t)cpl;
             int r = 0, a = 0, bb = 1, L = 2, s0 = 0;
             if (t < P) {
@@ -756,8 +820,8 @@ __global__ __launch_bounds__(BK_THREADS) void k_bucket(Params p, BatchArgs ba)
 #pragma unroll
             for (int q = 0; q < BK_PAIR_CHUNK; ++q) {
                 if (q >= cpl) break;
-                pa[q] = min(s0 + a, BK_CAP - 1);
-                pb[q] = min(s0 + bb, BK_CAP - 1);
+                pa[q] = min(s0 + a, CAP - 1);
+                pb[q] = min(s0 + bb, CAP - 1);
                 ++bb;
                 const bool wrapRow = bb == L;
                 a += wrapRow;
@@ -824,7 +888,7 @@ __global__ __launch_bounds__(BK_THREADS) void k_bucket(Params p, BatchArgs ba)
                     ++slot;
                 }
             }
-            if (t0 + BK_THREADS * (uint32_t)cpl < P) out.maybe_flush(BK_OUT / 2);
+            if (t0 + TH * (uint32_t)cpl < P) out.maybe_flush(BK_OUT / 2);
         }
         out.maybe_flush(BK_OUT / 2);
     }
