@@ -13,6 +13,12 @@ msm_status run_enumerate(msm_ctx* ctx, const uint64_t* S, int64_t n, int ell, in
     uint64_t valid[MAXW];
     std::vector<Combo> combos;
     build_tables(ell, k, h, bm, valid, combos);
+    // grouping on fewer blocks when it needs fewer passes
+    std::vector<Combo> parts;
+    std::vector<uint64_t> fam;
+    int jsel = 0;
+    const bool hier = build_hier_tables(ell, k, h, n, bm, valid, parts, fam, jsel);
+    if (hier) combos.swap(parts);
     const int C = (int)combos.size();
 
     // Partition shape.
@@ -32,6 +38,7 @@ msm_status run_enumerate(msm_ctx* ctx, const uint64_t* S, int64_t n, int ell, in
 
     msm::Carver cv;
     cv.take<Combo>((size_t)C);
+    cv.take<uint64_t>(std::max<size_t>(1, fam.size()));
     cv.take<uint64_t>((size_t)k * MAXW);
     cv.take<unsigned long long>(4);
     cv.take<uint32_t>(4);
@@ -47,6 +54,7 @@ msm_status run_enumerate(msm_ctx* ctx, const uint64_t* S, int64_t n, int ell, in
     msm::Carver c2;
     c2.base = static_cast<char*>(scr);
     Combo* d_combos = c2.take<Combo>((size_t)C);
+    uint64_t* d_fam = c2.take<uint64_t>(std::max<size_t>(1, fam.size()));
     uint64_t* d_bm = c2.take<uint64_t>((size_t)k * MAXW);
     unsigned long long* d_counter = c2.take<unsigned long long>(4);
     uint32_t* d_ovfc = c2.take<uint32_t>(4);
@@ -58,6 +66,8 @@ msm_status run_enumerate(msm_ctx* ctx, const uint64_t* S, int64_t n, int ell, in
     uint64_t* d_tile0 = c2.take<uint64_t>((size_t)Cg * nb + 1);
 
     MSM_HIP(ctx, hipMemcpyAsync(d_combos, combos.data(), sizeof(Combo) * C, hipMemcpyHostToDevice, stream));
+    if (!fam.empty())
+        MSM_HIP(ctx, hipMemcpyAsync(d_fam, fam.data(), sizeof(uint64_t) * fam.size(), hipMemcpyHostToDevice, stream));
     MSM_HIP(ctx, hipMemcpyAsync(d_bm, bm.data(), sizeof(uint64_t) * bm.size(), hipMemcpyHostToDevice, stream));
     hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, stream, d_counter, 4);
 
@@ -83,6 +93,14 @@ msm_status run_enumerate(msm_ctx* ctx, const uint64_t* S, int64_t n, int ell, in
     p.counter = d_counter;
     p.ovf = d_ovf;
     p.ovf_count = d_ovfc;
+    p.hier = hier ? 1 : 0;
+    p.jblk = jsel;
+    p.kmask = k >= 64 ? ~0ull : ((1ull << k) - 1);
+    p.blk_r = ell % k;
+    p.blk_L = ell / k;
+    p.blk_m1 = ((1ull << 32) + (uint64_t)(p.blk_L + 1) - 1) / (uint64_t)(p.blk_L + 1);
+    p.blk_m0 = ((1ull << 32) + (uint64_t)p.blk_L - 1) / (uint64_t)p.blk_L;
+    p.fam = hier ? d_fam : nullptr;
     p.list = d_ovf;
     p.list_count = d_ovfc;
     p.ovf2 = d_ovf2;

@@ -40,6 +40,8 @@
 #include "msm_internal.h"
 
 #include <algorithm>
+#include <cmath>
+#include <map>
 #include <vector>
 
 namespace {
@@ -73,12 +75,14 @@ constexpr int large_maxb()
     return W <= 2 ? 8 : 4;
 }
 
-struct Combo {                    // one set B of masked blocks
+struct Combo {                    // one set B of masked blocks (or, grouped
+                                  // hierarchically, one set A of kept blocks)
     uint64_t keep[MAXW];          // characters below ell outside the blocks of B
     uint64_t hi;                  // blocks of B above the smallest block not in B
     int32_t nhi;                  // number of blocks in hi
-    int32_t pad0;
-    uint64_t pad1[2];
+    int32_t nfam;                 // hierarchical: difference sets of the family
+    uint64_t amask;               // hierarchical: the kept blocks A
+    uint64_t famoff;              // hierarchical: first family entry in Params::fam
     uint64_t himask[MAXHI][MAXW]; // character masks of the first MAXHI blocks of hi
 };
 static_assert(sizeof(Combo) == 192, "Combo layout");
@@ -109,6 +113,13 @@ struct Params {
     unsigned long long* counter;
     Ovf* ovf;
     uint32_t* ovf_count;
+    // hierarchical grouping on j blocks (see hier_ok)
+    int hier;                // 0: one group per combination of masked blocks
+    int jblk;                // j, the kept blocks of a partition
+    uint64_t kmask;          // the k blocks as bits
+    int blk_r, blk_L;        // the first blk_r blocks hold blk_L + 1 characters, the rest blk_L
+    uint64_t blk_m1, blk_m0; // 2^32 / (blk_L + 1) and 2^32 / blk_L, rounded up
+    const uint64_t* fam;     // minimal difference sets of each partition's family
     // second pass over the overflow list (k_bucket with LIST)
     const Ovf* list;
     const uint32_t* list_count;
@@ -399,8 +410,11 @@ __global__ __launch_bounds__(PART_THREADS) void k_bpart_scatter(Params p, BatchA
 // Exact pair test of one candidate (see the file comment).
 
 template <int W>
+__device__ __forceinline__ bool hier_ok(const uint64_t (&x)[W], const Params& p, uint64_t amask);
+
+template <int W>
 __device__ __forceinline__ bool pair_ok(const uint64_t* a, const uint64_t* b, const Params& p,
-                                        const uint64_t (&keep)[W], uint64_t hi,
+                                        const uint64_t (&keep)[W], uint64_t hi, uint64_t amask,
                                         const uint64_t* __restrict__ bmL)
 {
     uint64_t x[W];
@@ -413,6 +427,7 @@ __device__ __forceinline__ bool pair_ok(const uint64_t* a, const uint64_t* b, co
         outside |= x[w] & keep[w];
     }
     bool ok = (ham <= p.h) && (outside == 0);
+    if (p.hier) return ok && hier_ok<W>(x, p, amask);
     uint64_t need = hi;
     while (ok && need) {
         const int blk = __builtin_ctzll(need);
@@ -431,7 +446,7 @@ __device__ __forceinline__ bool pair_ok(const uint64_t* a, const uint64_t* b, co
 template <int W>
 __device__ __forceinline__ bool pair_ok_fast(const uint64_t* a, const uint64_t* b, const Params& p,
                                              const uint64_t (&keep)[W], const uint64_t (&hm)[MAXHI][W], int nhi,
-                                             uint64_t hi_rest, const uint64_t* __restrict__ bmL)
+                                             uint64_t hi_rest, uint64_t amask, const uint64_t* __restrict__ bmL)
 {
     uint64_t x[W];
     int ham = 0;
@@ -443,6 +458,10 @@ __device__ __forceinline__ bool pair_ok_fast(const uint64_t* a, const uint64_t* 
         outside |= x[w] & keep[w];
     }
     bool ok = (ham <= p.h) & (outside == 0);
+    if (p.hier) {
+        if (ok) ok = hier_ok<W>(x, p, amask);
+        return ok;
+    }
 #pragma unroll
     for (int s = 0; s < MAXHI; ++s) {
         uint64_t any = 0;
@@ -478,6 +497,51 @@ __device__ __forceinline__ bool far_in_earlier(const Params& p, uint32_t i, uint
         if (ham <= p.h) return false;
     }
     return true;
+}
+
+// -------------------------------------------------------------------------
+// Hierarchical grouping (the concluding remarks' shared sorting, here one
+// level): instead of one grouping per set B of h masked blocks, points are
+// grouped by j < k - h blocks A, which serves every B whose unmasked blocks
+// contain A. A pair with differing blocks D (|D| <= h) has the canonical
+// set B*(D) = D plus the smallest blocks not in D (h in all); it is written
+// only in the partition whose A is the j smallest blocks not in B*(D), so
+// every pair is still written once. A partition's family is the set of D
+// that map to it; a run whose varying blocks contain no member of the family
+// cannot hold a pair to write.
+
+__device__ __forceinline__ int block_of(const Params& p, int c)
+{
+    const int split = p.blk_r * (p.blk_L + 1);
+    return c < split ? (int)(((uint64_t)c * p.blk_m1) >> 32)
+                     : p.blk_r + (int)(((uint64_t)(c - split) * p.blk_m0) >> 32);
+}
+
+// Whether the pair with difference x (at most h set bits) belongs to the
+// partition of kept blocks amask.
+template <int W>
+__device__ __forceinline__ bool hier_ok(const uint64_t (&x)[W], const Params& p, uint64_t amask)
+{
+    uint64_t D = 0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+        uint64_t v = x[w];
+        while (v) {
+            D |= 1ull << block_of(p, 64 * w + __builtin_ctzll(v));
+            v &= v - 1;
+        }
+    }
+    uint64_t B = D, fill = p.kmask & ~D;
+    for (int t = __popcll(D); t < p.h; ++t) {
+        B |= fill & (~fill + 1);
+        fill &= fill - 1;
+    }
+    uint64_t U = p.kmask & ~B, A = 0;
+    for (int t = 0; t < p.jblk; ++t) {
+        A |= U & (~U + 1);
+        U &= U - 1;
+    }
+    return A == amask;
 }
 
 // -------------------------------------------------------------------------
@@ -536,11 +600,17 @@ __global__ __launch_bounds__(TH, (TH == BK_THREADS && W <= 2 && DIGIT <= 10) ? 4
     uint64_t hm[MAXHI][W];
     int hb[MAXHI];
     uint64_t hi_rest = 0;
+    uint64_t amask = 0;
+    int nfam = 0;
+    const uint64_t* fam = nullptr;
     auto load_combo = [&](int c) {
         const Combo* cb = p.combos + c;
         load_keep<W>(cb, keep);
         hi = cb->hi;
         nhi = cb->nhi;
+        amask = cb->amask;
+        nfam = cb->nfam;
+        fam = p.fam ? p.fam + cb->famoff : nullptr;
 #pragma unroll
         for (int s2 = 0; s2 < MAXHI; ++s2)
 #pragma unroll
@@ -729,48 +799,68 @@ __global__ __launch_bounds__(TH, (TH == BK_THREADS && W <= 2 && DIGIT <= 10) ? 4
         }
         const uint32_t nruns = (uint32_t)(claimRun >> 32);
         __syncthreads();
-        // Each member marks the blocks of hi in which it differs from the
-        // run's first member; the histogram is cleared for the next bucket.
+        // Each member marks the blocks of hi (hierarchically: all blocks) in
+        // which it differs from the run's first member; the histogram is
+        // cleared for the next bucket.
 #pragma unroll
         for (int b = 0; b < MAXB; ++b) {
             if (b * TH < m && rank[b] != 0xFFFFFFFFu) {
-                if (hi && c[b] >= 2 && rank[b] > 0) {
+                if ((hi || p.hier) && c[b] >= 2 && rank[b] > 0) {
                     const uint32_t first = rfirst[b];
                     const uint32_t q = first + rank[b];
                     uint64_t x[W];
 #pragma unroll
                     for (int w = 0; w < W; ++w) x[w] = sl[q * W + w] ^ sl[first * W + w];
                     uint64_t bits = 0;
+                    if (p.hier) {
+                        // every block in which the member differs from the first
+                        for (int blk = 0; blk < p.k; ++blk) {
+                            uint64_t any = 0;
 #pragma unroll
-                    for (int s2 = 0; s2 < MAXHI; ++s2) {
-                        uint64_t any = 0;
+                            for (int w = 0; w < W; ++w) any |= x[w] & bmL[blk * W + w];
+                            bits |= any ? (1ull << blk) : 0ull;
+                        }
+                        if (bits) atomicOr(&runBlk[rrun[b]], (unsigned long long)bits);
+                    } else {
 #pragma unroll
-                        for (int w = 0; w < W; ++w) any |= x[w] & hm[s2][w];
-                        bits |= (s2 < nhi && any) ? (1ull << hb[s2]) : 0ull;
+                        for (int s2 = 0; s2 < MAXHI; ++s2) {
+                            uint64_t any = 0;
+#pragma unroll
+                            for (int w = 0; w < W; ++w) any |= x[w] & hm[s2][w];
+                            bits |= (s2 < nhi && any) ? (1ull << hb[s2]) : 0ull;
+                        }
+                        uint64_t need = hi_rest;
+                        while (need) {
+                            const int blk = __builtin_ctzll(need);
+                            need &= need - 1;
+                            uint64_t any = 0;
+#pragma unroll
+                            for (int w = 0; w < W; ++w) any |= x[w] & bmL[blk * W + w];
+                            bits |= any ? (1ull << blk) : 0ull;
+                        }
+                        if (bits) atomicOr(&runBlk[rrun[b]], (unsigned long long)bits);
                     }
-                    uint64_t need = hi_rest;
-                    while (need) {
-                        const int blk = __builtin_ctzll(need);
-                        need &= need - 1;
-                        uint64_t any = 0;
-#pragma unroll
-                        for (int w = 0; w < W; ++w) any |= x[w] & bmL[blk * W + w];
-                        bits |= any ? (1ull << blk) : 0ull;
-                    }
-                    if (bits) atomicOr(&runBlk[rrun[b]], (unsigned long long)bits);
                 }
                 hist[dig[b]] = 0;
             }
         }
         if (nruns == 0) continue;
-        if (hi) __syncthreads();
+        if (hi || p.hier) __syncthreads();
 
         // Each run claims its pairs, unless it cannot hold a pair to write:
         // a pair is written only if it differs in every block of `hi`, so a
         // block of `hi` that is constant over the whole run rules it out.
         for (uint32_t r = threadIdx.x; r < nruns; r += TH) {
             const int s0 = runS[r], L = runL[r];
-            const bool live = (runBlk[r] & hi) == hi;
+            bool live;
+            if (p.hier) {
+                // some difference set of the family fits in the run's varying blocks
+                const uint64_t v = runBlk[r];
+                live = nfam < 0;  // no family stored: keep every run
+                for (int f = 0; f < nfam; ++f) live |= (fam[f] & ~v) == 0ull;
+            } else {
+                live = (runBlk[r] & hi) == hi;
+            }
             if (live) {
                 const unsigned long long old =
                     atomicAdd(&claimPair, (1ull << 32) | (unsigned long long)(L * (L - 1) / 2));
@@ -843,7 +933,8 @@ __global__ __launch_bounds__(TH, (TH == BK_THREADS && W <= 2 && DIGIT <= 10) ? 4
                 const bool live = t + q < P;
                 pi[q] = idxB[pa[q]];
                 pj[q] = idxB[pb[q]];
-                const bool ok = live & pair_ok_fast<W>(&sl[pa[q] * W], &sl[pb[q] * W], p, keep, hm, nhi, hi_rest, bmL);
+                const bool ok =
+                    live & pair_ok_fast<W>(&sl[pa[q] * W], &sl[pb[q] * W], p, keep, hm, nhi, hi_rest, amask, bmL);
                 okbits |= (uint32_t)ok << q;
             }
             if (p.rep > 0 && okbits) {
@@ -946,7 +1037,7 @@ __device__ __forceinline__ void big_tile(const Params& p, const Ovf& e, int64_t 
     for (int jj = 0; jj < ncol; ++jj) {
         const uint64_t kc = sh.kC[jj];
         bool ok = rv && (!diag || jj > (int)threadIdx.x) && (uint32_t)(kc >> 32) == mine;
-        if (ok) ok = pair_ok<W>(&sh.sR[threadIdx.x * W], &sh.sC[jj * W], p, keep, hi, sh.bmL);
+        if (ok) ok = pair_ok<W>(&sh.sR[threadIdx.x * W], &sh.sC[jj * W], p, keep, hi, cb->amask, sh.bmL);
         const uint32_t jv = (uint32_t)kc;
         if (ok && p.rep > 0) ok = far_in_earlier<W>(p, ii, jv);
         out.push(ok, (ii < jv ? ii : jv) - o_off, (ii < jv ? jv : ii) - o_off);
@@ -1138,6 +1229,70 @@ inline void build_tables(int ell, int k, int h, std::vector<uint64_t>& bm, uint6
             for (int u = t + 1; u < h; ++u) sel[u] = sel[u - 1] + 1;
         }
     }
+}
+
+// Partitions of the hierarchical grouping on j blocks (see hier_ok) with
+// each one's family of difference sets, reduced to its minimal members.
+// The smallest j is taken whose kept characters (j * floor(ell / k)) reach
+// log2(n) + 8, so that unrelated points rarely share a group; returns false
+// when no such j needs fewer groupings than the C(k, h) combinations, or
+// when k is too large to list the difference sets.
+inline bool build_hier_tables(int ell, int k, int h, int64_t n, const std::vector<uint64_t>& bm,
+                              const uint64_t (&valid)[MAXW], std::vector<Combo>& parts, std::vector<uint64_t>& fam,
+                              int& jsel)
+{
+    if (k > 16 || h < 1 || k - h < 1) return false;
+    const uint64_t kmask = (1ull << k) - 1;
+    const double need = std::log2((double)std::max<int64_t>(n, 2)) + 8.0;
+    const int64_t ncomb = binom(k, h);
+    for (int j = 1; j <= k - h; ++j) {
+        if ((double)(j * (ell / k)) < need) continue;
+        std::map<uint64_t, std::vector<uint64_t>> fams;
+        for (uint64_t D = 0; D <= kmask; ++D) {
+            if (__builtin_popcountll(D) > h) continue;
+            uint64_t B = D, fill = kmask & ~D;
+            for (int t = __builtin_popcountll(D); t < h; ++t) {
+                B |= fill & (~fill + 1);
+                fill &= fill - 1;
+            }
+            uint64_t U = kmask & ~B, A = 0;
+            for (int t = 0; t < j; ++t) {
+                A |= U & (~U + 1);
+                U &= U - 1;
+            }
+            fams[A].push_back(D);
+        }
+        if ((int64_t)fams.size() >= ncomb) return false;  // a larger j only adds partitions
+        parts.clear();
+        fam.clear();
+        for (const auto& kv : fams) {
+            Combo cb{};
+            for (int w = 0; w < MAXW; ++w) {
+                uint64_t kw = 0;
+                for (int b = 0; b < k; ++b)
+                    if ((kv.first >> b) & 1ull) kw |= bm[(size_t)b * MAXW + w];
+                cb.keep[w] = kw & valid[w];
+            }
+            cb.hi = 0;
+            cb.nhi = 0;
+            cb.amask = kv.first;
+            cb.famoff = fam.size();
+            for (uint64_t D : kv.second) {
+                bool minimal = true;
+                for (uint64_t E : kv.second)
+                    if (E != D && (E & ~D) == 0) {
+                        minimal = false;
+                        break;
+                    }
+                if (minimal) fam.push_back(D);
+            }
+            cb.nfam = (int32_t)(fam.size() - cb.famoff);
+            parts.push_back(cb);
+        }
+        jsel = j;
+        return true;
+    }
+    return false;
 }
 
 }  // namespace
