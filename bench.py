@@ -82,7 +82,8 @@ def algorithmic(kernel, w, n, C, mH, mE, W):
     """(amount, unit, bound) of algorithmic work per launch of a kernel.
 
     Units per launch: a launch of the partition and bucket kernels covers n
-    points under each of the C combinations; k_verify covers the mH
+    points under each of the C groupings (C(k, h) combinations of masked
+    blocks, or the hierarchical groupings that replace them); k_verify covers the mH
     candidate pairs and the n rows; k_project_f32 the n x d x ell products.
     """
     sb = 8 * W  # bytes of one string
@@ -261,9 +262,8 @@ def run_mixture(msm, ctx, w, X, Xd, project, steps, warmup, judge_sub=None):
 
     n, W = Xd.shape[0], (w.ell + 63) // 64
     S = torch.empty((n, W), dtype=torch.int64, device=Xd.device)
-    C = 1
-    for t in range(w.h):
-        C = C * (w.k - t) // (t + 1)
+    # groupings the enumeration makes (C(k, h), or fewer hierarchical ones)
+    C, jblk = msm.msm_enumerate_groupings(n, w.ell, w.k, w.h)
     # size the output buffers with a count-only pass
     project(S)
     _, mH = msm.msm_enumerate_pairs(ctx, S, w.ell, w.k, w.h, cap=0)
@@ -297,7 +297,7 @@ def run_mixture(msm, ctx, w, X, Xd, project, steps, warmup, judge_sub=None):
     t_enum = sum(v["ms_per_step"] for k, v in phase.items()
                  if k in ("k_part_count", "k_part_scan", "k_part_scatter", "k_bucket", "k_big"))
     missing = missing_edge_ratio(msm, ctx, w, Xd, pairs[:mH], verified[:mE], sub=judge_sub)
-    res = {"ms_per_step": ms_step, "points_per_s": n / (ms_step / 1e3), "combinations": C,
+    res = {"ms_per_step": ms_step, "points_per_s": n / (ms_step / 1e3), "combinations": C, "hier_j": jblk,
            "hamming_pairs": int(mH), "eps_pairs": int(mE), "phase": phase,
            "hamming_pairs_per_s_enumerate": (mH / (t_enum / 1e3)) if t_enum else None,
            "eps_pairs_per_s_total": mE / (ms_step / 1e3), "missing_edge_ratio": missing}
@@ -657,7 +657,8 @@ def main():
         "dtype": "f32",
         "data": f"synthetic Gaussian mixture, sigma_mode={args.sigma_mode}",
         "config": {"workload": w.name, "n": n, "d": w.d, "ell": w.ell, "k": w.k, "h": w.h, "eps": w.eps,
-                   "metric": w.metric, "combinations": res["combinations"], "sigma_mode": args.sigma_mode},
+                   "metric": w.metric, "groupings": res["combinations"], "hier_j": res["hier_j"],
+                   "sigma_mode": args.sigma_mode},
         "edges_per_s": {"hamming_pairs_per_s_enumerate": c["hamming_pairs_per_s_enumerate"],
                         "eps_pairs_per_s_total": c["eps_pairs_per_s_total"]},
         "counts": {"hamming_pairs": res["hamming_pairs"], "eps_pairs": res["eps_pairs"]},

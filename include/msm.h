@@ -119,7 +119,10 @@ msm_status msm_project_lowp(msm_ctx* ctx, const float* X, int64_t n, int32_t d, 
  * nearly equal length (the first ell mod k blocks get one extra bit), and
  * for each of the C(k, h) sets B of masked blocks the strings are grouped by
  * their unmasked part; pairs inside a group are tested and each pair is
- * written under exactly one B, so the output has no duplicates.
+ * written under exactly one B, so the output has no duplicates. When it
+ * takes fewer passes the strings are instead grouped on sets of j blocks
+ * shared by several B (see msm_enumerate_groupings); the output is the
+ * same set.
  *   S      DEVICE uint64[n * W]       input strings
  *   pairs  DEVICE uint32[2 * cap]     output pairs; may be NULL when cap == 0
  *   m_out  HOST   int64               number of pairs (always written on OK
@@ -135,6 +138,19 @@ msm_status msm_project_lowp(msm_ctx* ctx, const float* X, int64_t n, int32_t d, 
 msm_status msm_enumerate_pairs(msm_ctx* ctx, const uint64_t* S, int64_t n, int32_t ell,
                                int32_t k, int32_t h, uint32_t* pairs, int64_t cap,
                                int64_t* m_out, void* stream);
+
+/* How msm_enumerate_pairs groups n strings of ell bits for (k, h): the
+ * number of groupings (partition passes) it makes and, when it groups on
+ * j < k - h blocks (hierarchically: one grouping on a set A of j blocks
+ * serves every combination of masked blocks whose unmasked blocks contain
+ * A; taken when j * floor(ell / k) >= log2(n) + 8 and it needs fewer
+ * groupings than C(k, h)), that j; else *jblocks = 0 and *groupings =
+ * C(k, h). Host-only, needs no context or device.
+ *   groupings, jblocks  HOST int32
+ * Errors: MSM_E_INVALID for NULL outputs or arguments outside the limits of
+ * msm_enumerate_pairs. */
+msm_status msm_enumerate_groupings(int64_t n, int32_t ell, int32_t k, int32_t h, int32_t* groupings,
+                                   int32_t* jblocks);
 
 /* Union of the Hamming pairs of Q independent string pools, Section 4.1,
  * eq. (5): E = E_1 u ... u E_Q with E_q = {(i, j) : i < j,

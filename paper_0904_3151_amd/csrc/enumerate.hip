@@ -237,3 +237,25 @@ extern "C" msm_status msm_enumerate_replicates(msm_ctx* ctx, const uint64_t* S, 
 {
     return enumerate_entry("msm_enumerate_replicates", ctx, S, n, ell, Q, k, h, pairs, cap, m_out, stream);
 }
+
+extern "C" msm_status msm_enumerate_groupings(int64_t n, int32_t ell, int32_t k, int32_t h, int32_t* groupings,
+                                              int32_t* jblocks)
+{
+    if (!groupings || !jblocks || n < 0 || ell < 1 || ell > 256 || h < 0 || k <= h || k > ell || k > MAXK ||
+        binom(k, h) > 65536)
+        return MSM_E_INVALID;
+    std::vector<uint64_t> bm;
+    uint64_t valid[MAXW];
+    std::vector<Combo> combos, parts;
+    std::vector<uint64_t> fam;
+    build_tables(ell, k, h, bm, valid, combos);
+    int jsel = 0;
+    if (build_hier_tables(ell, k, h, n, bm, valid, parts, fam, jsel)) {
+        *groupings = (int32_t)parts.size();
+        *jblocks = jsel;
+    } else {
+        *groupings = (int32_t)combos.size();
+        *jblocks = 0;
+    }
+    return MSM_OK;
+}

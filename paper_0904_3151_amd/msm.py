@@ -39,7 +39,7 @@ DTYPES = {"f32": F32, "bf16": BF16, "fp8": FP8_E4M3, "fp8_e4m3": FP8_E4M3}
 METRICS = {"euclidean": EUCLIDEAN, "cosine": COSINE}
 
 EXPORTS = ("msm_version", "msm_create", "msm_destroy", "msm_last_error",
-           "msm_project", "msm_project_lowp", "msm_enumerate_pairs", "msm_enumerate_replicates",
+           "msm_project", "msm_project_lowp", "msm_enumerate_pairs", "msm_enumerate_replicates", "msm_enumerate_groupings",
            "msm_verify", "msm_bruteforce_eps",
            "msm_project_mlp", "msm_mlp_loss_grad", "msm_mlp_adam", "msm_mlp_train",
            "msm_batch_create", "msm_batch_run", "msm_batch_launch_graph", "msm_batch_tuning",
@@ -96,6 +96,8 @@ def _load():
     lib.msm_enumerate_pairs.restype = i32
     lib.msm_enumerate_replicates.argtypes = [vp, vp, i64, i32, i32, i32, i32, vp, i64, ctypes.POINTER(i64), vp]
     lib.msm_enumerate_replicates.restype = i32
+    lib.msm_enumerate_groupings.argtypes = [i64, i32, i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    lib.msm_enumerate_groupings.restype = i32
     lib.msm_verify.argtypes = [vp, vp, i64, i32, i64, vp, i64, i32, ctypes.c_float, vp, i64,
                                ctypes.POINTER(i64), vp]
     lib.msm_verify.restype = i32
@@ -265,6 +267,17 @@ def msm_enumerate_pairs(ctx: Context, S: torch.Tensor, ell: int, k: int, h: int,
                                   ctypes.byref(m), _stream(stream))
     _check(ctx, st, m.value)
     return (pairs[: m.value] if pairs is not None else None), m.value
+
+
+def msm_enumerate_groupings(n: int, ell: int, k: int, h: int):
+    """(groupings, j) msm_enumerate_pairs uses for n strings (j = 0: one
+    grouping per combination of masked blocks)."""
+    g = ctypes.c_int32(0)
+    j = ctypes.c_int32(0)
+    st = _lib.msm_enumerate_groupings(int(n), int(ell), int(k), int(h), ctypes.byref(g), ctypes.byref(j))
+    if st != MSM_OK:
+        raise MSMError(st, "msm_enumerate_groupings: invalid arguments")
+    return g.value, j.value
 
 
 def msm_enumerate_replicates(ctx: Context, S: torch.Tensor, ell: int, k: int, h: int,

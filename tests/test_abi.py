@@ -53,3 +53,19 @@ def test_create_without_device_fails_cleanly(msm):
     assert st in (msm.MSM_E_INVALID, msm.MSM_E_HIP)
     assert not h.value
     assert msm.lib().msm_last_error(None)
+
+
+def test_enumerate_groupings_host_only():
+    """The grouping plan is host logic: C(k, h) groupings, or fewer
+    hierarchical ones on j blocks when j * floor(ell / k) >= log2(n) + 8
+    (15 for ell = 128, k = 8, h = 4, j = 2; 10 for ell = 60, k = 6, h = 2,
+    j = 3; counted by enumerating every difference set by hand)."""
+    from paper_0904_3151_amd import msm
+    assert msm.msm_enumerate_groupings(1_000_000, 128, 8, 4) == (15, 2)
+    assert msm.msm_enumerate_groupings(20_000, 60, 6, 2) == (10, 3)
+    assert msm.msm_enumerate_groupings(4_000_000, 240, 10, 8) == (45, 0)   # j = 2 needs 45 = C(10, 8)
+    assert msm.msm_enumerate_groupings(200_000, 64, 5, 3) == (10, 0)
+    assert msm.msm_enumerate_groupings(3000, 16, 16, 2) == (120, 0)        # blocks of one bit
+    assert msm.msm_enumerate_groupings(10, 10, 3, 0) == (1, 0)             # h = 0
+    with pytest.raises(msm.MSMError):
+        msm.msm_enumerate_groupings(100, 64, 3, 3)
