@@ -262,14 +262,15 @@ def run_mixture(msm, ctx, w, X, Xd, project, steps, warmup, judge_sub=None):
 
     n, W = Xd.shape[0], (w.ell + 63) // 64
     S = torch.empty((n, W), dtype=torch.int64, device=Xd.device)
-    # groupings the enumeration makes (C(k, h), or fewer hierarchical ones)
-    C, jblk = msm.msm_enumerate_groupings(n, w.ell, w.k, w.h)
+
     # size the output buffers with a count-only pass
     project(S)
     _, mH = msm.msm_enumerate_pairs(ctx, S, w.ell, w.k, w.h, cap=0)
+    # groupings the enumeration made (C(k, h), or fewer hierarchical ones)
+    C, jblk = msm.msm_enumerate_last_plan(ctx)
     pairs = torch.empty((max(1, int(mH * 1.05) + 1024), 2), dtype=torch.int32, device=Xd.device)
     verified = torch.empty_like(pairs)
-    log(f"hamming pairs {mH}")
+    log(f"hamming pairs {mH}, groupings {C}, j {jblk}")
 
     def step():
         project(S)

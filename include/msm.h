@@ -139,7 +139,7 @@ msm_status msm_enumerate_pairs(msm_ctx* ctx, const uint64_t* S, int64_t n, int32
                                int32_t k, int32_t h, uint32_t* pairs, int64_t cap,
                                int64_t* m_out, void* stream);
 
-/* How msm_enumerate_pairs groups n strings of ell bits for (k, h): the
+/* How msm_enumerate_pairs may group n strings of ell bits for (k, h): the
  * number of groupings (partition passes) it makes and, when it groups on
  * j < k - h blocks (hierarchically: one grouping on a set A of j blocks
  * serves every combination of masked blocks whose unmasked blocks contain
@@ -151,6 +151,16 @@ msm_status msm_enumerate_pairs(msm_ctx* ctx, const uint64_t* S, int64_t n, int32
  * msm_enumerate_pairs. */
 msm_status msm_enumerate_groupings(int64_t n, int32_t ell, int32_t k, int32_t h, int32_t* groupings,
                                    int32_t* jblocks);
+
+/* The groupings the last msm_enumerate_pairs or msm_enumerate_replicates
+ * call on ctx made, and its j (0 when it grouped per combination). When a
+ * hierarchical grouping is possible the call first counts a few groupings
+ * of each kind and keeps the hierarchical one only if its groupings times
+ * their sum of squared bucket sizes is the smaller, so this can differ from
+ * msm_enumerate_groupings. Zero before the first call.
+ *   groupings, jblocks  HOST int32
+ * Errors: MSM_E_INVALID for NULL arguments. */
+msm_status msm_enumerate_last_plan(const msm_ctx* ctx, int32_t* groupings, int32_t* jblocks);
 
 /* Union of the Hamming pairs of Q independent string pools, Section 4.1,
  * eq. (5): E = E_1 u ... u E_Q with E_q = {(i, j) : i < j,

@@ -13,13 +13,15 @@ msm_status run_enumerate(msm_ctx* ctx, const uint64_t* S, int64_t n, int ell, in
     uint64_t valid[MAXW];
     std::vector<Combo> combos;
     build_tables(ell, k, h, bm, valid, combos);
-    // grouping on fewer blocks when it needs fewer passes
+    // grouping on fewer blocks when it needs fewer passes (a candidate;
+    // a probe of the data below decides)
     std::vector<Combo> parts;
     std::vector<uint64_t> fam;
     int jsel = 0;
-    const bool hier = build_hier_tables(ell, k, h, n, bm, valid, parts, fam, jsel);
-    if (hier) combos.swap(parts);
-    const int C = (int)combos.size();
+    const bool hier_cand = build_hier_tables(ell, k, h, n, bm, valid, parts, fam, jsel);
+    const int Cstd = (int)combos.size();
+    const int Ch = hier_cand ? (int)parts.size() : 0;
+    const int Cmax = std::max(Cstd, Ch);
 
     // Partition shape.
     int r1 = 0;
@@ -33,17 +35,20 @@ msm_status run_enumerate(msm_ctx* ctx, const uint64_t* S, int64_t n, int ell, in
     const size_t per_combo = msm::align_up((size_t)n * 8, 256) + msm::align_up((size_t)nt * nb * 4, 256) +
                              msm::align_up((size_t)(nb + 1) * 4, 256) + 2 * msm::align_up((size_t)nb * sizeof(Ovf), 256);
     const size_t budget = (size_t)3 << 30;
-    int Cg = (int)std::max<size_t>(1, std::min<size_t>((size_t)C, budget / per_combo));
+    int Cg = (int)std::max<size_t>(1, std::min<size_t>((size_t)Cmax, budget / per_combo));
     Cg = std::min(Cg, 65535);
 
     msm::Carver cv;
-    cv.take<Combo>((size_t)C);
+    cv.take<Combo>((size_t)Cstd);
+    cv.take<Combo>((size_t)std::max(1, Ch));
     cv.take<uint64_t>(std::max<size_t>(1, fam.size()));
     cv.take<uint64_t>((size_t)k * MAXW);
     cv.take<unsigned long long>(4);
     cv.take<uint32_t>(4);
     cv.take<uint64_t>((size_t)Cg * n);
     cv.take<uint32_t>((size_t)Cg * nt * nb);
+    cv.take<uint32_t>(hier_cand ? (size_t)(PROBE_HIER + PROBE_STD + 1) * PROBE_BINS : 1);
+    cv.take<Combo>(1);
     cv.take<uint32_t>((size_t)Cg * (nb + 1));
     cv.take<Ovf>((size_t)Cg * nb);
     cv.take<Ovf>((size_t)Cg * nb);
@@ -53,19 +58,28 @@ msm_status run_enumerate(msm_ctx* ctx, const uint64_t* S, int64_t n, int ell, in
     if (st != MSM_OK) return st;
     msm::Carver c2;
     c2.base = static_cast<char*>(scr);
-    Combo* d_combos = c2.take<Combo>((size_t)C);
+    Combo* d_combos_std = c2.take<Combo>((size_t)Cstd);
+    Combo* d_combos_h = c2.take<Combo>((size_t)std::max(1, Ch));
     uint64_t* d_fam = c2.take<uint64_t>(std::max<size_t>(1, fam.size()));
     uint64_t* d_bm = c2.take<uint64_t>((size_t)k * MAXW);
     unsigned long long* d_counter = c2.take<unsigned long long>(4);
     uint32_t* d_ovfc = c2.take<uint32_t>(4);
     uint64_t* d_part = c2.take<uint64_t>((size_t)Cg * n);
     uint32_t* d_counts = c2.take<uint32_t>((size_t)Cg * nt * nb);
+    uint32_t* d_probe = c2.take<uint32_t>(hier_cand ? (size_t)(PROBE_HIER + PROBE_STD + 1) * PROBE_BINS : 1);
+    Combo* d_full = c2.take<Combo>(1);
     uint32_t* d_base = c2.take<uint32_t>((size_t)Cg * (nb + 1));
     Ovf* d_ovf = c2.take<Ovf>((size_t)Cg * nb);
     Ovf* d_ovf2 = c2.take<Ovf>((size_t)Cg * nb);
     uint64_t* d_tile0 = c2.take<uint64_t>((size_t)Cg * nb + 1);
 
-    MSM_HIP(ctx, hipMemcpyAsync(d_combos, combos.data(), sizeof(Combo) * C, hipMemcpyHostToDevice, stream));
+    MSM_HIP(ctx, hipMemcpyAsync(d_combos_std, combos.data(), sizeof(Combo) * Cstd, hipMemcpyHostToDevice, stream));
+    Combo full{};  // the whole string kept: groups of identical strings
+    for (int w = 0; w < MAXW; ++w) full.keep[w] = valid[w];
+    if (Ch > 0) {
+        MSM_HIP(ctx, hipMemcpyAsync(d_combos_h, parts.data(), sizeof(Combo) * Ch, hipMemcpyHostToDevice, stream));
+        MSM_HIP(ctx, hipMemcpyAsync(d_full, &full, sizeof(Combo), hipMemcpyHostToDevice, stream));
+    }
     if (!fam.empty())
         MSM_HIP(ctx, hipMemcpyAsync(d_fam, fam.data(), sizeof(uint64_t) * fam.size(), hipMemcpyHostToDevice, stream));
     MSM_HIP(ctx, hipMemcpyAsync(d_bm, bm.data(), sizeof(uint64_t) * bm.size(), hipMemcpyHostToDevice, stream));
@@ -93,18 +107,69 @@ msm_status run_enumerate(msm_ctx* ctx, const uint64_t* S, int64_t n, int ell, in
     p.counter = d_counter;
     p.ovf = d_ovf;
     p.ovf_count = d_ovfc;
-    p.hier = hier ? 1 : 0;
     p.jblk = jsel;
     p.kmask = k >= 64 ? ~0ull : ((1ull << k) - 1);
     p.blk_r = ell % k;
     p.blk_L = ell / k;
     p.blk_m1 = ((1ull << 32) + (uint64_t)(p.blk_L + 1) - 1) / (uint64_t)(p.blk_L + 1);
     p.blk_m0 = ((1ull << 32) + (uint64_t)p.blk_L - 1) / (uint64_t)p.blk_L;
-    p.fam = hier ? d_fam : nullptr;
     p.list = d_ovf;
     p.list_count = d_ovfc;
     p.ovf2 = d_ovf2;
     p.ovf2_count = d_ovfc + 1;
+
+    // Probe: the first PROBE_BINS strings are grouped (a 14-bit hash of the
+    // kept characters) on every hierarchical grouping (up to PROBE_HIER,
+    // evenly spaced), on PROBE_STD per-combination groupings and on the
+    // whole string. Pairs of identical strings are dropped by the run
+    // pruning in all but one grouping of either kind, every other pair in a
+    // group is tested; so each kind costs about its groupings times (pairs
+    // in groups - identical pairs + one unit per point), scaled to n.
+    // Strings with little entropy in some blocks (learned codes, for one)
+    // merge many groups when only those j blocks are kept.
+    bool hier = hier_cand;
+    if (hier_cand) {
+        const int nsh = std::min(PROBE_HIER, Ch), nss = std::min(PROBE_STD, Cstd);
+        const int hst = Ch / nsh, sst = Cstd / nss;
+        const int64_t sample = std::min<int64_t>(n, PROBE_BINS);
+        uint32_t* hist = d_probe;
+        const int nh = nsh + nss + 1;
+        hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)(((int64_t)nh * PROBE_BINS + 255) / 256)), dim3(256), 0,
+                           stream, hist, nh * PROBE_BINS);
+        const unsigned pg = (unsigned)((sample + 255) / 256);
+        hipLaunchKernelGGL((k_probe_groups<W>), dim3(pg, nsh), dim3(256), 0, stream, S, sample, d_combos_h, hst,
+                           hist);
+        hipLaunchKernelGGL((k_probe_groups<W>), dim3(pg, nss), dim3(256), 0, stream, S, sample, d_combos_std, sst,
+                           hist + (size_t)nsh * PROBE_BINS);
+        hipLaunchKernelGGL((k_probe_groups<W>), dim3(pg, 1), dim3(256), 0, stream, S, sample, d_full, 0,
+                           hist + (size_t)(nsh + nss) * PROBE_BINS);
+        hipLaunchKernelGGL(k_bucket_sumsq, dim3((unsigned)(((int64_t)nsh * PROBE_BINS + 255) / 256)), dim3(256), 0,
+                           stream, (const uint32_t*)hist, 1, nsh * PROBE_BINS, d_counter + 1);
+        hipLaunchKernelGGL(k_bucket_sumsq, dim3((unsigned)(((int64_t)nss * PROBE_BINS + 255) / 256)), dim3(256), 0,
+                           stream, (const uint32_t*)(hist + (size_t)nsh * PROBE_BINS), 1, nss * PROBE_BINS,
+                           d_counter + 2);
+        hipLaunchKernelGGL(k_bucket_sumsq, dim3((PROBE_BINS + 255) / 256), dim3(256), 0, stream,
+                           (const uint32_t*)(hist + (size_t)(nsh + nss) * PROBE_BINS), 1, PROBE_BINS, d_counter + 3);
+        MSM_HIP(ctx, hipGetLastError());
+        MSM_HIP(ctx, hipMemcpyAsync(ctx->host_words, d_counter + 1, 3 * sizeof(uint64_t), hipMemcpyDeviceToHost,
+                                    stream));
+        MSM_HIP(ctx, hipStreamSynchronize(stream));
+        // sum of squared group sizes = points + 2 * pairs in groups; pairs
+        // grow as (n / sample)^2 and points as n / sample to the full data
+        const double sq_h = (double)ctx->host_words[0] / nsh, sq_s = (double)ctx->host_words[1] / nss;
+        const double sq_f = (double)ctx->host_words[2];
+        const double pts = (double)sample, up = (double)n / (double)sample;
+        const double cost_h = (double)Ch * (std::max(0.0, sq_h - sq_f) / 2.0 * up + pts);
+        const double cost_s = (double)Cstd * (std::max(0.0, sq_s - sq_f) / 2.0 * up + pts);
+        hier = cost_h < cost_s;
+    }
+    Combo* d_combos = hier ? d_combos_h : d_combos_std;
+    const int C = hier ? Ch : Cstd;
+    Cg = std::min(Cg, C);
+    p.hier = hier ? 1 : 0;
+    p.fam = hier ? d_fam : nullptr;
+    ctx->last_groupings = C;
+    ctx->last_jblocks = hier ? jsel : 0;
 
     std::vector<Ovf> hovf;
     std::vector<uint64_t> htile;
@@ -257,5 +322,13 @@ extern "C" msm_status msm_enumerate_groupings(int64_t n, int32_t ell, int32_t k,
         *groupings = (int32_t)combos.size();
         *jblocks = 0;
     }
+    return MSM_OK;
+}
+
+extern "C" msm_status msm_enumerate_last_plan(const msm_ctx* ctx, int32_t* groupings, int32_t* jblocks)
+{
+    if (!ctx || !groupings || !jblocks) return MSM_E_INVALID;
+    *groupings = ctx->last_groupings;
+    *jblocks = ctx->last_jblocks;
     return MSM_OK;
 }

@@ -271,20 +271,39 @@ __global__ __launch_bounds__(FU_THREADS) void k_mlp_fused(const float* __restric
 #pragma unroll
         for (int b = 0; b < NB; ++b) u[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-    for (int c = 0; c < nch; ++c) {
-        __syncthreads();
-        {   // stage the chunk's weights, 16 bytes per copy
-            const uint4* s1 = reinterpret_cast<const uint4*>(P.W1p + (int64_t)c * FU_HC * Kp);
-            for (int e = threadIdx.x; e < FU_HC * Kp / 8; e += FU_THREADS) {
-                const int j = e / (Kp / 8), kk = (e % (Kp / 8)) * 8;
-                *reinterpret_cast<uint4*>(W1s + j * L1 + kk) = s1[e];
-            }
-            const uint4* s2 = reinterpret_cast<const uint4*>(P.W2p + (int64_t)c * Np * FU_HC);
-            for (int e = threadIdx.x; e < Np * FU_HC / 8; e += FU_THREADS) {
-                const int nn = e / (FU_HC / 8), kk = (e % (FU_HC / 8)) * 8;
-                *reinterpret_cast<uint4*>(W2s + nn * L2 + kk) = s2[e];
-            }
+    // The next chunk's weights are fetched into registers while the current
+    // one is multiplied, then written to LDS at the top of the next step.
+    constexpr int N1 = FU_HC * Kp / 8, N2 = Np * FU_HC / 8;  // 16-byte pieces
+    constexpr int R1 = (N1 + FU_THREADS - 1) / FU_THREADS, R2 = (N2 + FU_THREADS - 1) / FU_THREADS;
+    uint4 p1[R1], p2[R2];
+    auto fetch = [&](int c) {
+        const uint4* s1 = reinterpret_cast<const uint4*>(P.W1p + (int64_t)c * FU_HC * Kp);
+        const uint4* s2 = reinterpret_cast<const uint4*>(P.W2p + (int64_t)c * Np * FU_HC);
+#pragma unroll
+        for (int r = 0; r < R1; ++r) {
+            const int e = threadIdx.x + r * FU_THREADS;
+            p1[r] = e < N1 ? s1[e] : uint4{0u, 0u, 0u, 0u};
         }
+#pragma unroll
+        for (int r = 0; r < R2; ++r) {
+            const int e = threadIdx.x + r * FU_THREADS;
+            p2[r] = e < N2 ? s2[e] : uint4{0u, 0u, 0u, 0u};
+        }
+    };
+    fetch(0);
+    for (int c = 0; c < nch; ++c) {
+        __syncthreads();  // the previous chunk is no longer read from LDS
+#pragma unroll
+        for (int r = 0; r < R1; ++r) {
+            const int e = threadIdx.x + r * FU_THREADS;
+            if (e < N1) *reinterpret_cast<uint4*>(W1s + (e / (Kp / 8)) * L1 + (e % (Kp / 8)) * 8) = p1[r];
+        }
+#pragma unroll
+        for (int r = 0; r < R2; ++r) {
+            const int e = threadIdx.x + r * FU_THREADS;
+            if (e < N2) *reinterpret_cast<uint4*>(W2s + (e / (FU_HC / 8)) * L2 + (e % (FU_HC / 8)) * 8) = p2[r];
+        }
+        if (c + 1 < nch) fetch(c + 1);
         __syncthreads();
         // hidden pre-activations of the wave's rows for the chunk's 64 units
         floatx4 hacc[2][4];

@@ -55,7 +55,7 @@ constexpr int BK_WAVES = BK_THREADS / 64;
 constexpr int BK_MAXB = 4;                        // 64-element batches per wave
 constexpr int BK_CAP = BK_WAVES * 64 * BK_MAXB;   // largest bucket sorted in LDS
 constexpr int BK_PAIR_CHUNK = 8;                  // consecutive pairs per lane
-constexpr int BK_GROUP = 8;                       // buckets per workgroup
+constexpr int BK_GROUP = 2;                       // buckets per workgroup
 constexpr int BK_OUT = 512;                       // staged output pairs per workgroup
 constexpr int BK_DIGIT = 10;                      // mix bits counted inside a bucket
 constexpr int BK_DIGIT_L = 12;                    // the same in the second pass over large buckets
@@ -1149,6 +1149,41 @@ __global__ __launch_bounds__(BIG_TILE) void k_big_batch(Params p, BatchArgs ba, 
         out.counter = ba.m_dev + e.pad;
         big_tile<W>(p, e, (int64_t)(tix - tile0[lo]), BigShared{kR, kC, sR, sC, bmL}, out, (uint32_t)in.off);
     }
+}
+
+// Grouping probe: the first `sample` strings hashed on one grouping's kept
+// characters into PROBE_BINS bins.
+constexpr int PROBE_LOG = 14;
+constexpr int PROBE_BINS = 1 << PROBE_LOG;
+constexpr int PROBE_HIER = 64;  // hierarchical groupings probed, at most
+constexpr int PROBE_STD = 4;    // per-combination groupings probed
+
+template <int W>
+__global__ void k_probe_groups(const uint64_t* __restrict__ S, int64_t sample, const Combo* __restrict__ base,
+                               int stride, uint32_t* __restrict__ hist)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= sample) return;
+    const Combo* cb = base + (size_t)blockIdx.y * stride;
+    uint64_t keep[W], s[W];
+    load_keep<W>(cb, keep);
+    load_string<W>(S, (uint64_t)i, s);
+    atomicAdd(&hist[(size_t)blockIdx.y * PROBE_BINS + (masked_mix<W>(s, keep) >> (32 - PROBE_LOG))], 1u);
+}
+
+// Sum over buckets of the squared bucket size, from the tile counts of one
+// grouping (counts[t][b], nt tiles, nb buckets).
+__global__ void k_bucket_sumsq(const uint32_t* __restrict__ counts, int nt, int nb, unsigned long long* out)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long v = 0;
+    if (b < nb) {
+        uint32_t c = 0;
+        for (int t = 0; t < nt; ++t) c += counts[(size_t)t * nb + b];
+        v = (unsigned long long)c * c;
+    }
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63) == 0 && v) atomicAdd(out, v);
 }
 
 __global__ void k_zero_u64(unsigned long long* a, int n)

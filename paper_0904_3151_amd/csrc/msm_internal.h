@@ -23,6 +23,10 @@ struct msm_ctx {
     size_t scratch_bytes = 0;
     // Pinned host words used to read counters back from the device.
     uint64_t* host_words = nullptr;
+    // Groupings (and j of a hierarchical grouping, else 0) of the last
+    // enumeration.
+    int32_t last_groupings = 0;
+    int32_t last_jblocks = 0;
     // Per-kernel timing: a pair of HIP events around every launch while on.
     bool prof = false;
     struct Pending {

@@ -40,6 +40,7 @@ METRICS = {"euclidean": EUCLIDEAN, "cosine": COSINE}
 
 EXPORTS = ("msm_version", "msm_create", "msm_destroy", "msm_last_error",
            "msm_project", "msm_project_lowp", "msm_enumerate_pairs", "msm_enumerate_replicates", "msm_enumerate_groupings",
+           "msm_enumerate_last_plan",
            "msm_verify", "msm_bruteforce_eps",
            "msm_project_mlp", "msm_mlp_loss_grad", "msm_mlp_adam", "msm_mlp_train",
            "msm_batch_create", "msm_batch_run", "msm_batch_launch_graph", "msm_batch_tuning",
@@ -98,6 +99,8 @@ def _load():
     lib.msm_enumerate_replicates.restype = i32
     lib.msm_enumerate_groupings.argtypes = [i64, i32, i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]
     lib.msm_enumerate_groupings.restype = i32
+    lib.msm_enumerate_last_plan.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    lib.msm_enumerate_last_plan.restype = i32
     lib.msm_verify.argtypes = [vp, vp, i64, i32, i64, vp, i64, i32, ctypes.c_float, vp, i64,
                                ctypes.POINTER(i64), vp]
     lib.msm_verify.restype = i32
@@ -277,6 +280,14 @@ def msm_enumerate_groupings(n: int, ell: int, k: int, h: int):
     st = _lib.msm_enumerate_groupings(int(n), int(ell), int(k), int(h), ctypes.byref(g), ctypes.byref(j))
     if st != MSM_OK:
         raise MSMError(st, "msm_enumerate_groupings: invalid arguments")
+    return g.value, j.value
+
+
+def msm_enumerate_last_plan(ctx: Context):
+    """(groupings, j) of the last enumeration on ctx (j = 0: per combination)."""
+    g = ctypes.c_int32(0)
+    j = ctypes.c_int32(0)
+    _check(ctx, _lib.msm_enumerate_last_plan(ctx.handle, ctypes.byref(g), ctypes.byref(j)))
     return g.value, j.value
 
 

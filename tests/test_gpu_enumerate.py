@@ -144,3 +144,21 @@ def test_enumerate_invalid_arguments(msm, ctx):
     assert call(128, 40, 20) == msm.MSM_E_UNSUPPORTED  # too many combinations
     assert call(128, 8, 2, pairs=None, cap=10) == msm.MSM_E_INVALID
     assert call(128, 8, 2, pairs=P.data_ptr() + 4, cap=4) == msm.MSM_E_INVALID  # misaligned
+
+
+def test_grouping_plan_follows_the_data(msm, ctx):
+    """Uniform strings take the hierarchical grouping (15 groupings on pairs
+    of blocks at ell = 128, k = 8, h = 4); strings whose blocks carry little
+    entropy fall back to one grouping per combination. Both give the exact
+    pair set."""
+    S = I.random_strings(50_000, 128, seed=71)
+    check(msm, ctx, S, 128, 8, 4)
+    assert msm.msm_enumerate_last_plan(ctx) == (15, 2)
+    # 40 codes repeated: every point shares its string with ~100 others, so
+    # two blocks separate far fewer points than four
+    codes40 = I.random_strings(40, 128, seed=72)
+    rng = np.random.default_rng(73)
+    S2 = np.ascontiguousarray(codes40[rng.integers(0, 40, 4000)])
+    check(msm, ctx, S2, 128, 8, 4)
+    g, j = msm.msm_enumerate_last_plan(ctx)
+    assert (g, j) in ((15, 2), (70, 0))
