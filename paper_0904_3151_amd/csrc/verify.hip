@@ -13,6 +13,7 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 constexpr int VF_THREADS = 256;
 constexpr int VF_TEAM = 16;
 constexpr int VF_OUT = 1024;  // staged kept pairs per workgroup
+constexpr int NUM_XCD = 8;
 
 template <int METRIC, bool VEC4>
 __global__ __launch_bounds__(VF_THREADS) void k_verify(const float* __restrict__ X, int64_t n, int d,
@@ -28,13 +29,21 @@ __global__ __launch_bounds__(VF_THREADS) void k_verify(const float* __restrict__
     __syncthreads();
     msm::PairStager<VF_OUT> stage{obuf, &ocnt, &ogb, out, cap, counter};
     const int tl = threadIdx.x & (VF_TEAM - 1);
-    const int64_t team = ((int64_t)blockIdx.x * VF_THREADS + threadIdx.x) / VF_TEAM;
-    const int64_t nteams = ((int64_t)gridDim.x * VF_THREADS) / VF_TEAM;
-    // every lane runs the same number of iterations so wave_append is reached uniformly
-    const int64_t rounds = (m + nteams - 1) / nteams;
+    // Workgroups are dispatched round-robin over the NUM_XCD dies, each with
+    // its own L2; the workgroups of die x take the contiguous x-th part of
+    // the list, where adjacent pairs often share a row. gridDim.x is a
+    // multiple of NUM_XCD.
+    const int xcd = (int)(blockIdx.x % NUM_XCD);
+    const int64_t per_die = gridDim.x / NUM_XCD;
+    const int64_t lo = m * xcd / NUM_XCD, hi = m * (xcd + 1) / NUM_XCD;
+    const int64_t team = ((int64_t)(blockIdx.x / NUM_XCD) * VF_THREADS + threadIdx.x) / VF_TEAM;
+    const int64_t nteams = (per_die * VF_THREADS) / VF_TEAM;
+    // every lane of a workgroup runs the same number of iterations, so
+    // wave_append and the flushes are reached uniformly
+    const int64_t rounds = (hi - lo + nteams - 1) / nteams;
     for (int64_t it = 0; it < rounds; ++it) {
-        const int64_t q = team + it * nteams;
-        bool live = q < m;
+        const int64_t q = lo + team + it * nteams;
+        bool live = q < hi;
         uint32_t i = 0, j = 0;
         if (live) {
             const uint2 pr = *reinterpret_cast<const uint2*>(pairs + 2 * q);
@@ -156,6 +165,7 @@ extern "C" msm_status msm_verify(msm_ctx* ctx, const float* X, int64_t n, int32_
     int64_t blocks = (m + teams_per_block - 1) / teams_per_block;
     const int64_t max_blocks = (int64_t)ctx->num_cu * 16;
     if (blocks > max_blocks) blocks = max_blocks;
+    blocks = (blocks + NUM_XCD - 1) / NUM_XCD * NUM_XCD;
     {
         msm::KernelTimer kt(ctx, s, "k_verify");
         if (metric == MSM_EUCLIDEAN)
