@@ -602,7 +602,7 @@ void launch_loss_grad(hipStream_t s, const float* X, int d, int64_t ldx, const f
         gemm<EPI_BIAS_TANH>(s, a);
     }
     hipLaunchKernelGGL(k_pair_loss, dim3(blocks(B, 4)), dim3(256), 0, s, t.U, ell, B, labels, h, lam, t.dA2, loss);
-    const int splits = (int)std::min<int64_t>(64, std::max<int64_t>(1, P / 512));
+    const int splits = (int)std::min<int64_t>(256, std::max<int64_t>(1, P / 128));
     {   // gW2 = g^T dA2
         GemmArgs a{};
         a.M = hid; a.N = ell; a.K = (int)P;
@@ -627,7 +627,7 @@ void launch_loss_grad(hipStream_t s, const float* X, int d, int64_t ldx, const f
         a.C = gW1; a.ldc = hid;
         gemm<EPI_ATOMIC>(s, a, splits);
     }
-    const int64_t rpb = std::max<int64_t>(256, (P + 16383) / 16384);
+    const int64_t rpb = std::max<int64_t>(32, (P + 16383) / 16384);
     const unsigned gy = (unsigned)((P + rpb - 1) / rpb);
     hipLaunchKernelGGL(k_colsum, dim3(blocks(ell), gy), dim3(256), 0, s, t.dA2, P, ell, rpb, gb2);
     hipLaunchKernelGGL(k_colsum, dim3(blocks(hid), gy), dim3(256), 0, s, t.dA1, P, hid, rpb, gb1);

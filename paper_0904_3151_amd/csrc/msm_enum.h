@@ -926,13 +926,11 @@ __global__ __launch_bounds__(TH, (TH == BK_THREADS && W <= 2 && DIGIT <= 10) ? 4
                 }
             }
             uint32_t okbits = 0;
-            uint32_t pi[BK_PAIR_CHUNK], pj[BK_PAIR_CHUNK];
+            // point indices are read from LDS only for the pairs that pass
 #pragma unroll
             for (int q = 0; q < BK_PAIR_CHUNK; ++q) {
                 if (q >= cpl) break;
                 const bool live = t + q < P;
-                pi[q] = idxB[pa[q]];
-                pj[q] = idxB[pb[q]];
                 const bool ok =
                     live & pair_ok_fast<W>(&sl[pa[q] * W], &sl[pb[q] * W], p, keep, hm, nhi, hi_rest, amask, bmL);
                 okbits |= (uint32_t)ok << q;
@@ -941,7 +939,8 @@ __global__ __launch_bounds__(TH, (TH == BK_THREADS && W <= 2 && DIGIT <= 10) ? 4
 #pragma unroll
                 for (int q = 0; q < BK_PAIR_CHUNK; ++q) {
                     if (q >= cpl) break;
-                    if (((okbits >> q) & 1u) && !far_in_earlier<W>(p, pi[q], pj[q])) okbits &= ~(1u << q);
+                    if (((okbits >> q) & 1u) && !far_in_earlier<W>(p, idxB[pa[q]], idxB[pb[q]]))
+                        okbits &= ~(1u << q);
                 }
             }
             // one append per lane per chunk: wave prefix of the counts, one
@@ -968,8 +967,9 @@ __global__ __launch_bounds__(TH, (TH == BK_THREADS && W <= 2 && DIGIT <= 10) ? 4
             for (int q = 0; q < BK_PAIR_CHUNK; ++q) {
                 if (q >= cpl) break;
                 if ((okbits >> q) & 1u) {
-                    const uint32_t lo2 = (pi[q] < pj[q] ? pi[q] : pj[q]) - o_off;
-                    const uint32_t hi3 = (pi[q] < pj[q] ? pj[q] : pi[q]) - o_off;
+                    const uint32_t iq = idxB[pa[q]], jq = idxB[pb[q]];
+                    const uint32_t lo2 = (iq < jq ? iq : jq) - o_off;
+                    const uint32_t hi3 = (iq < jq ? jq : iq) - o_off;
                     if (slot < (uint32_t)BK_OUT) {
                         obuf[slot] = make_uint2(lo2, hi3);
                     } else {
