@@ -17,8 +17,9 @@ msm_status run_enumerate(msm_ctx* ctx, const uint64_t* S, int64_t n, int ell, in
     // a probe of the data below decides)
     std::vector<Combo> parts;
     std::vector<uint64_t> fam;
+    std::vector<uint32_t> dtab;
     int jsel = 0;
-    const bool hier_cand = build_hier_tables(ell, k, h, n, bm, valid, parts, fam, jsel);
+    const bool hier_cand = build_hier_tables(ell, k, h, n, bm, valid, parts, fam, dtab, jsel);
     const int Cstd = (int)combos.size();
     const int Ch = hier_cand ? (int)parts.size() : 0;
     const int Cmax = std::max(Cstd, Ch);
@@ -42,6 +43,7 @@ msm_status run_enumerate(msm_ctx* ctx, const uint64_t* S, int64_t n, int ell, in
     cv.take<Combo>((size_t)Cstd);
     cv.take<Combo>((size_t)std::max(1, Ch));
     cv.take<uint64_t>(std::max<size_t>(1, fam.size()));
+    cv.take<uint32_t>(std::max<size_t>(1, dtab.size()));
     cv.take<uint64_t>((size_t)k * MAXW);
     cv.take<unsigned long long>(4);
     cv.take<uint32_t>(4);
@@ -61,6 +63,7 @@ msm_status run_enumerate(msm_ctx* ctx, const uint64_t* S, int64_t n, int ell, in
     Combo* d_combos_std = c2.take<Combo>((size_t)Cstd);
     Combo* d_combos_h = c2.take<Combo>((size_t)std::max(1, Ch));
     uint64_t* d_fam = c2.take<uint64_t>(std::max<size_t>(1, fam.size()));
+    uint32_t* d_dtab = c2.take<uint32_t>(std::max<size_t>(1, dtab.size()));
     uint64_t* d_bm = c2.take<uint64_t>((size_t)k * MAXW);
     unsigned long long* d_counter = c2.take<unsigned long long>(4);
     uint32_t* d_ovfc = c2.take<uint32_t>(4);
@@ -82,6 +85,9 @@ msm_status run_enumerate(msm_ctx* ctx, const uint64_t* S, int64_t n, int ell, in
     }
     if (!fam.empty())
         MSM_HIP(ctx, hipMemcpyAsync(d_fam, fam.data(), sizeof(uint64_t) * fam.size(), hipMemcpyHostToDevice, stream));
+    if (!dtab.empty())
+        MSM_HIP(ctx,
+                hipMemcpyAsync(d_dtab, dtab.data(), sizeof(uint32_t) * dtab.size(), hipMemcpyHostToDevice, stream));
     MSM_HIP(ctx, hipMemcpyAsync(d_bm, bm.data(), sizeof(uint64_t) * bm.size(), hipMemcpyHostToDevice, stream));
     hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, stream, d_counter, 4);
 
@@ -107,10 +113,9 @@ msm_status run_enumerate(msm_ctx* ctx, const uint64_t* S, int64_t n, int ell, in
     p.counter = d_counter;
     p.ovf = d_ovf;
     p.ovf_count = d_ovfc;
-    p.jblk = jsel;
-    p.kmask = k >= 64 ? ~0ull : ((1ull << k) - 1);
     p.blk_r = ell % k;
     p.blk_L = ell / k;
+    p.dL = (p.blk_r == 0 && (p.blk_L == 8 || p.blk_L == 16 || p.blk_L == 32)) ? p.blk_L : 0;
     p.blk_m1 = ((1ull << 32) + (uint64_t)(p.blk_L + 1) - 1) / (uint64_t)(p.blk_L + 1);
     p.blk_m0 = ((1ull << 32) + (uint64_t)p.blk_L - 1) / (uint64_t)p.blk_L;
     p.list = d_ovf;
@@ -168,6 +173,7 @@ msm_status run_enumerate(msm_ctx* ctx, const uint64_t* S, int64_t n, int ell, in
     Cg = std::min(Cg, C);
     p.hier = hier ? 1 : 0;
     p.fam = hier ? d_fam : nullptr;
+    p.dtab = hier ? d_dtab : nullptr;
     ctx->last_groupings = C;
     ctx->last_jblocks = hier ? jsel : 0;
 
@@ -313,9 +319,10 @@ extern "C" msm_status msm_enumerate_groupings(int64_t n, int32_t ell, int32_t k,
     uint64_t valid[MAXW];
     std::vector<Combo> combos, parts;
     std::vector<uint64_t> fam;
+    std::vector<uint32_t> dtab;
     build_tables(ell, k, h, bm, valid, combos);
     int jsel = 0;
-    if (build_hier_tables(ell, k, h, n, bm, valid, parts, fam, jsel)) {
+    if (build_hier_tables(ell, k, h, n, bm, valid, parts, fam, dtab, jsel)) {
         *groupings = (int32_t)parts.size();
         *jblocks = jsel;
     } else {

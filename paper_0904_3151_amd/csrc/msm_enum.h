@@ -65,6 +65,8 @@ constexpr int MAX_BUCKETS = 8192;
 constexpr int TARGET_BUCKET = 512;
 
 constexpr int MAXHI = 4;   // blocks of `hi` tested from unrolled masks
+constexpr int DT_LDS_K = 12;  // family bitmaps over up to 2^12 difference sets are read from LDS
+constexpr int DT_LDS_WORDS = 1 << (DT_LDS_K - 5);
 
 // Threads and points per thread of the second bucket pass, sized so that
 // its LDS stays below 160 KB (capacity 4096 points for W <= 2, else 2048).
@@ -81,8 +83,9 @@ struct Combo {                    // one set B of masked blocks (or, grouped
     uint64_t hi;                  // blocks of B above the smallest block not in B
     int32_t nhi;                  // number of blocks in hi
     int32_t nfam;                 // hierarchical: difference sets of the family
-    uint64_t amask;               // hierarchical: the kept blocks A
-    uint64_t famoff;              // hierarchical: first family entry in Params::fam
+    uint64_t amask;               // hierarchical: the partition's blocks A
+    uint32_t famoff;              // hierarchical: first family entry in Params::fam
+    uint32_t dtoff;               // hierarchical: first word of its bitmap in Params::dtab
     uint64_t himask[MAXHI][MAXW]; // character masks of the first MAXHI blocks of hi
 };
 static_assert(sizeof(Combo) == 192, "Combo layout");
@@ -113,13 +116,13 @@ struct Params {
     unsigned long long* counter;
     Ovf* ovf;
     uint32_t* ovf_count;
-    // hierarchical grouping on j blocks (see hier_ok)
+    // hierarchical grouping on j blocks (see diff_blocks)
     int hier;                // 0: one group per combination of masked blocks
-    int jblk;                // j, the kept blocks of a partition
-    uint64_t kmask;          // the k blocks as bits
     int blk_r, blk_L;        // the first blk_r blocks hold blk_L + 1 characters, the rest blk_L
     uint64_t blk_m1, blk_m0; // 2^32 / (blk_L + 1) and 2^32 / blk_L, rounded up
+    int dL;                  // 8, 16 or 32 when every block has that many characters, else 0
     const uint64_t* fam;     // minimal difference sets of each partition's family
+    const uint32_t* dtab;    // per partition, a bitmap over difference sets D: D is in its family
     // second pass over the overflow list (k_bucket with LIST)
     const Ovf* list;
     const uint32_t* list_count;
@@ -410,11 +413,12 @@ __global__ __launch_bounds__(PART_THREADS) void k_bpart_scatter(Params p, BatchA
 // Exact pair test of one candidate (see the file comment).
 
 template <int W>
-__device__ __forceinline__ bool hier_ok(const uint64_t (&x)[W], const Params& p, uint64_t amask);
+__device__ __forceinline__ uint32_t diff_blocks(const uint64_t (&x)[W], const Params& p);
+__device__ __forceinline__ bool in_family(const uint32_t* tab, uint32_t D);
 
 template <int W>
 __device__ __forceinline__ bool pair_ok(const uint64_t* a, const uint64_t* b, const Params& p,
-                                        const uint64_t (&keep)[W], uint64_t hi, uint64_t amask,
+                                        const uint64_t (&keep)[W], uint64_t hi, const uint32_t* dtab,
                                         const uint64_t* __restrict__ bmL)
 {
     uint64_t x[W];
@@ -427,7 +431,7 @@ __device__ __forceinline__ bool pair_ok(const uint64_t* a, const uint64_t* b, co
         outside |= x[w] & keep[w];
     }
     bool ok = (ham <= p.h) && (outside == 0);
-    if (p.hier) return ok && hier_ok<W>(x, p, amask);
+    if (p.hier) return ok && in_family(dtab, diff_blocks<W>(x, p));
     uint64_t need = hi;
     while (ok && need) {
         const int blk = __builtin_ctzll(need);
@@ -446,7 +450,8 @@ __device__ __forceinline__ bool pair_ok(const uint64_t* a, const uint64_t* b, co
 template <int W>
 __device__ __forceinline__ bool pair_ok_fast(const uint64_t* a, const uint64_t* b, const Params& p,
                                              const uint64_t (&keep)[W], const uint64_t (&hm)[MAXHI][W], int nhi,
-                                             uint64_t hi_rest, uint64_t amask, const uint64_t* __restrict__ bmL)
+                                             uint64_t hi_rest, const uint32_t* dtabL, const uint32_t* dtabG,
+                                             const uint64_t* __restrict__ bmL)
 {
     uint64_t x[W];
     int ham = 0;
@@ -459,8 +464,12 @@ __device__ __forceinline__ bool pair_ok_fast(const uint64_t* a, const uint64_t* 
     }
     bool ok = (ham <= p.h) & (outside == 0);
     if (p.hier) {
-        if (ok) ok = hier_ok<W>(x, p, amask);
-        return ok;
+        // the pair's difference set must be in the partition's family
+        uint32_t D = 0;
+        if (p.dL) D = diff_blocks<W>(x, p);
+        else if (ok) D = diff_blocks<W>(x, p);
+        const uint32_t word = p.k <= DT_LDS_K ? dtabL[D >> 5] : dtabG[D >> 5];
+        return ok & (((word >> (D & 31)) & 1u) != 0u);
     }
 #pragma unroll
     for (int s = 0; s < MAXHI; ++s) {
@@ -507,8 +516,9 @@ __device__ __forceinline__ bool far_in_earlier(const Params& p, uint32_t i, uint
 // set B*(D) = D plus the smallest blocks not in D (h in all); it is written
 // only in the partition whose A is the j smallest blocks not in B*(D), so
 // every pair is still written once. A partition's family is the set of D
-// that map to it; a run whose varying blocks contain no member of the family
-// cannot hold a pair to write.
+// that map to it: a pair within distance h is written iff its D is in the
+// family (one bit of a per-partition bitmap), and a run whose varying blocks
+// contain no member of the family cannot hold a pair to write.
 
 __device__ __forceinline__ int block_of(const Params& p, int c)
 {
@@ -517,31 +527,59 @@ __device__ __forceinline__ int block_of(const Params& p, int c)
                      : p.blk_r + (int)(((uint64_t)(c - split) * p.blk_m0) >> 32);
 }
 
-// Whether the pair with difference x (at most h set bits) belongs to the
-// partition of kept blocks amask.
+// The blocks in which a pair differs, as a bit mask, from its differing
+// characters x. With blocks of 8, 16 or 32 characters each block is one
+// field of a 32-bit half-word: a field is nonzero iff its top bit is set or
+// adding all-ones to its lower bits carries into the top bit (the sum stays
+// inside the field), and the top bits are then gathered into consecutive
+// bits. Other layouts visit the set characters one by one; the caller does
+// that only for pairs within distance h, so at most h of them.
 template <int W>
-__device__ __forceinline__ bool hier_ok(const uint64_t (&x)[W], const Params& p, uint64_t amask)
+__device__ __forceinline__ uint32_t diff_blocks(const uint64_t (&x)[W], const Params& p)
 {
-    uint64_t D = 0;
+    uint32_t D = 0;
+    if (p.dL == 16) {
 #pragma unroll
-    for (int w = 0; w < W; ++w) {
-        uint64_t v = x[w];
-        while (v) {
-            D |= 1ull << block_of(p, 64 * w + __builtin_ctzll(v));
-            v &= v - 1;
+        for (int w = 0; w < W; ++w)
+#pragma unroll
+            for (int hf = 0; hf < 2; ++hf) {
+                const uint32_t v = (uint32_t)(x[w] >> (32 * hf));
+                const uint32_t t = (((v & 0x7FFF7FFFu) + 0x7FFF7FFFu) | v) & 0x80008000u;
+                D |= (((t >> 15) & 1u) | (t >> 30)) << (4 * w + 2 * hf);
+            }
+    } else if (p.dL == 8) {
+#pragma unroll
+        for (int w = 0; w < W; ++w)
+#pragma unroll
+            for (int hf = 0; hf < 2; ++hf) {
+                const uint32_t v = (uint32_t)(x[w] >> (32 * hf));
+                const uint32_t t = (((v & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | v) & 0x80808080u;
+                // top bits at 7, 15, 23, 31 -> 0, 8, 16, 24; the product puts
+                // them at 21..24 with no two partial products overlapping
+                D |= ((((t >> 7) * 0x00204081u) >> 21) & 0xFu) << (8 * w + 4 * hf);
+            }
+    } else if (p.dL == 32) {
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            D |= (uint32_t)((uint32_t)x[w] != 0u) << (2 * w);
+            D |= (uint32_t)((uint32_t)(x[w] >> 32) != 0u) << (2 * w + 1);
+        }
+    } else {
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            uint64_t v = x[w];
+            while (v) {
+                D |= 1u << block_of(p, 64 * w + __builtin_ctzll(v));
+                v &= v - 1;
+            }
         }
     }
-    uint64_t B = D, fill = p.kmask & ~D;
-    for (int t = __popcll(D); t < p.h; ++t) {
-        B |= fill & (~fill + 1);
-        fill &= fill - 1;
-    }
-    uint64_t U = p.kmask & ~B, A = 0;
-    for (int t = 0; t < p.jblk; ++t) {
-        A |= U & (~U + 1);
-        U &= U - 1;
-    }
-    return A == amask;
+    return D;
+}
+
+__device__ __forceinline__ bool in_family(const uint32_t* tab, uint32_t D)
+{
+    return ((tab[D >> 5] >> (D & 31)) & 1u) != 0u;
 }
 
 // -------------------------------------------------------------------------
@@ -584,6 +622,7 @@ __global__ __launch_bounds__(TH, (TH == BK_THREADS && W <= 2 && DIGIT <= 10) ? 4
     __shared__ uint16_t liveL[CAP / 2];
     __shared__ uint32_t liveP[CAP / 2];
     __shared__ uint64_t bmL[MAXK * W];
+    __shared__ uint32_t dtabL[DT_LDS_WORDS];
     __shared__ unsigned long long claimRun;   // runs << 32 | members
     __shared__ unsigned long long claimPair;  // live runs << 32 | pairs
     __shared__ uint2 obuf[BK_OUT];
@@ -600,17 +639,18 @@ __global__ __launch_bounds__(TH, (TH == BK_THREADS && W <= 2 && DIGIT <= 10) ? 4
     uint64_t hm[MAXHI][W];
     int hb[MAXHI];
     uint64_t hi_rest = 0;
-    uint64_t amask = 0;
     int nfam = 0;
     const uint64_t* fam = nullptr;
+    const uint32_t* dtabG = nullptr;  // the partition's family bitmap
+    int tab_c = -1;                   // the partition whose bitmap is in dtabL
     auto load_combo = [&](int c) {
         const Combo* cb = p.combos + c;
         load_keep<W>(cb, keep);
         hi = cb->hi;
         nhi = cb->nhi;
-        amask = cb->amask;
         nfam = cb->nfam;
         fam = p.fam ? p.fam + cb->famoff : nullptr;
+        dtabG = p.dtab ? p.dtab + cb->dtoff : nullptr;
 #pragma unroll
         for (int s2 = 0; s2 < MAXHI; ++s2)
 #pragma unroll
@@ -712,6 +752,12 @@ __global__ __launch_bounds__(TH, (TH == BK_THREADS && W <= 2 && DIGIT <= 10) ? 4
             }
         }
         __syncthreads();  // LDS of the previous bucket is free, hist is zero
+        if (p.hier && p.k <= DT_LDS_K && tab_c != cl) {
+            // the partition's bitmap, read only after the histogram's barrier
+            const int words = max(1, (1 << p.k) >> 5);
+            for (int e = threadIdx.x; e < words; e += TH) dtabL[e] = dtabG[e];
+            tab_c = cl;
+        }
         if (cnt < 2) continue;
         if (cnt > (uint32_t)CAP) {
             if (threadIdx.x == 0) {
@@ -932,7 +978,8 @@ __global__ __launch_bounds__(TH, (TH == BK_THREADS && W <= 2 && DIGIT <= 10) ? 4
                 if (q >= cpl) break;
                 const bool live = t + q < P;
                 const bool ok =
-                    live & pair_ok_fast<W>(&sl[pa[q] * W], &sl[pb[q] * W], p, keep, hm, nhi, hi_rest, amask, bmL);
+                    live & pair_ok_fast<W>(&sl[pa[q] * W], &sl[pb[q] * W], p, keep, hm, nhi, hi_rest, dtabL,
+                                                  dtabG, bmL);
                 okbits |= (uint32_t)ok << q;
             }
             if (p.rep > 0 && okbits) {
@@ -1037,7 +1084,8 @@ __device__ __forceinline__ void big_tile(const Params& p, const Ovf& e, int64_t 
     for (int jj = 0; jj < ncol; ++jj) {
         const uint64_t kc = sh.kC[jj];
         bool ok = rv && (!diag || jj > (int)threadIdx.x) && (uint32_t)(kc >> 32) == mine;
-        if (ok) ok = pair_ok<W>(&sh.sR[threadIdx.x * W], &sh.sC[jj * W], p, keep, hi, cb->amask, sh.bmL);
+        if (ok) ok = pair_ok<W>(&sh.sR[threadIdx.x * W], &sh.sC[jj * W], p, keep, hi,
+                                        p.dtab ? p.dtab + cb->dtoff : nullptr, sh.bmL);
         const uint32_t jv = (uint32_t)kc;
         if (ok && p.rep > 0) ok = far_in_earlier<W>(p, ii, jv);
         out.push(ok, (ii < jv ? ii : jv) - o_off, (ii < jv ? jv : ii) - o_off);
@@ -1266,15 +1314,19 @@ inline void build_tables(int ell, int k, int h, std::vector<uint64_t>& bm, uint6
     }
 }
 
-// Partitions of the hierarchical grouping on j blocks (see hier_ok) with
-// each one's family of difference sets, reduced to its minimal members.
-// The smallest j is taken whose kept characters (j * floor(ell / k)) reach
-// log2(n) + 8, so that unrelated points rarely share a group; returns false
-// when no such j needs fewer groupings than the C(k, h) combinations, or
-// when k is too large to list the difference sets.
+// Partitions of the hierarchical grouping on j blocks (see diff_blocks)
+// with each one's family of difference sets: its minimal members (fam, for
+// the run pruning) and all of them as a bitmap over the 2^k sets (dtab).
+// Every member of a family leaves the blocks outside the family's union
+// unchanged, so a partition groups on all of those, A among them: pairs
+// that differ there can never be written in it. The smallest j is taken
+// whose j * floor(ell / k) characters of A reach log2(n) + 8, so that
+// unrelated points rarely share a group; returns false when no such j needs
+// fewer groupings than the C(k, h) combinations, or when k is too large to
+// list the difference sets.
 inline bool build_hier_tables(int ell, int k, int h, int64_t n, const std::vector<uint64_t>& bm,
                               const uint64_t (&valid)[MAXW], std::vector<Combo>& parts, std::vector<uint64_t>& fam,
-                              int& jsel)
+                              std::vector<uint32_t>& dtab, int& jsel)
 {
     if (k > 16 || h < 1 || k - h < 1) return false;
     const uint64_t kmask = (1ull << k) - 1;
@@ -1300,18 +1352,26 @@ inline bool build_hier_tables(int ell, int k, int h, int64_t n, const std::vecto
         if ((int64_t)fams.size() >= ncomb) return false;  // a larger j only adds partitions
         parts.clear();
         fam.clear();
+        dtab.clear();
+        const size_t words = std::max<size_t>(1, ((size_t)1 << k) / 32);
         for (const auto& kv : fams) {
             Combo cb{};
+            uint64_t uni = 0;
+            for (uint64_t D : kv.second) uni |= D;
+            const uint64_t keepb = kmask & ~uni;  // contains A
             for (int w = 0; w < MAXW; ++w) {
                 uint64_t kw = 0;
                 for (int b = 0; b < k; ++b)
-                    if ((kv.first >> b) & 1ull) kw |= bm[(size_t)b * MAXW + w];
+                    if ((keepb >> b) & 1ull) kw |= bm[(size_t)b * MAXW + w];
                 cb.keep[w] = kw & valid[w];
             }
             cb.hi = 0;
             cb.nhi = 0;
             cb.amask = kv.first;
-            cb.famoff = fam.size();
+            cb.dtoff = (uint32_t)dtab.size();
+            dtab.resize(dtab.size() + words, 0u);
+            for (uint64_t D : kv.second) dtab[cb.dtoff + (D >> 5)] |= 1u << (D & 31);
+            cb.famoff = (uint32_t)fam.size();
             for (uint64_t D : kv.second) {
                 bool minimal = true;
                 for (uint64_t E : kv.second)

@@ -162,3 +162,22 @@ def test_grouping_plan_follows_the_data(msm, ctx):
     check(msm, ctx, S2, 128, 8, 4)
     g, j = msm.msm_enumerate_last_plan(ctx)
     assert (g, j) in ((15, 2), (70, 0))
+
+
+@pytest.mark.parametrize("ell,k,h,groupings", [
+    (128, 8, 4, 15),    # 16-character blocks, family bitmap in LDS
+    (96, 12, 3, 20),    # 8-character blocks, 2^12 difference sets
+    (128, 16, 3, 20),   # 8-character blocks, bitmap over 2^16 sets read from memory
+    (256, 16, 4, 15),   # four words
+    (128, 4, 1, 2),     # 32-character blocks
+    (60, 6, 2, 10),     # 10-character blocks: the difference set bit by bit
+    (130, 7, 3, 10),    # blocks of 19 and 18 characters
+])
+def test_hierarchical_layouts(msm, ctx, ell, k, h, groupings):
+    """The hierarchical grouping on every block layout its pair test
+    distinguishes: clusters of strings within a few flips of a seed, so
+    that many pairs fall on either side of distance h."""
+    S = I.random_strings(6000, ell, seed=ell * 17 + k, n_seeds=600, flips=h + 1)
+    assert check(msm, ctx, S, ell, k, h) > 0
+    g, j = msm.msm_enumerate_last_plan(ctx)
+    assert g == groupings and j > 0

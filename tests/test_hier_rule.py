@@ -8,7 +8,10 @@ unmasked blocks contain A. A pair whose strings differ in the blocks D
 h in all. The pair is written only in the grouping whose A is the j
 smallest blocks outside B*(D). It agrees on those blocks, so it meets in
 that grouping; and since A is a function of D, it is written exactly once.
-The number of distinct A is what msm_enumerate_groupings reports."""
+Every D that maps to A leaves the blocks outside the union of those D
+unchanged, so the grouping may key on all of those blocks (A among them)
+without losing a pair. The number of distinct A is what
+msm_enumerate_groupings reports."""
 import itertools
 import random
 
@@ -41,9 +44,21 @@ def partitions(k, h, j):
     return sorted({a_of(D, k, h, j) for D in range(1 << k) if bin(D).count("1") <= h})
 
 
+def key_blocks(A, k, h, j, widen):
+    """Blocks a partition groups on: A, or every block no family member touches."""
+    if not widen:
+        return A
+    union = 0
+    for D in range(1 << k):
+        if bin(D).count("1") <= h and a_of(D, k, h, j) == A:
+            union |= D
+    return ((1 << k) - 1) & ~union
+
+
+@pytest.mark.parametrize("widen", [False, True])
 @pytest.mark.parametrize("ell,k,h,j", [(16, 4, 2, 1), (16, 4, 2, 2), (60, 6, 2, 3), (64, 5, 3, 1),
                                        (128, 8, 4, 2), (40, 8, 3, 2), (33, 11, 1, 5)])
-def test_every_pair_written_once(ell, k, h, j):
+def test_every_pair_written_once(ell, k, h, j, widen):
     rnd = random.Random(ell * 7 + k * 3 + h + j)
     bm = block_masks(ell, k)
     seeds = [rnd.getrandbits(ell) for _ in range(60)]
@@ -56,9 +71,11 @@ def test_every_pair_written_once(ell, k, h, j):
     truth = {(a, b) for a in range(len(S)) for b in range(a + 1, len(S)) if bin(S[a] ^ S[b]).count("1") <= h}
     written = []
     for A in partitions(k, h, j):
+        kb = key_blocks(A, k, h, j, widen)
+        assert kb & A == A
         keep = 0
         for b in range(k):
-            if A >> b & 1:
+            if kb >> b & 1:
                 keep |= bm[b]
         groups = {}
         for i, s in enumerate(S):
