@@ -1,9 +1,15 @@
 // Distance verification of candidate pairs (Section 4.1, Definition 1.1).
 //
-// A team of 16 lanes handles one pair: each lane reads consecutive 16-byte
-// pieces of x_i and x_j (a team covers 256 contiguous bytes per row per
-// step), accumulates in FP32, and the team reduces with lane shuffles. The
-// team leaders then append the kept pairs with one atomic per wave.
+// A team of VF_TEAM lanes handles one pair: each lane reads consecutive
+// 16-byte pieces of x_i and x_j (a team covers VF_TEAM * 16 contiguous bytes
+// per row per step), four steps at a time so that eight loads per lane are
+// in flight, accumulates in FP32, and the team reduces with lane shuffles.
+// The next pair's indices are fetched while the current pair is computed.
+// The team leaders then append the kept pairs with one atomic per wave.
+//
+// The kernel is bound by the latency of the row gathers and by the
+// per-pair work every lane of a team repeats (indices, reduction, decision,
+// append): eight lanes per pair balance the two at d = 128.
 #include "msm_internal.h"
 
 namespace {
@@ -11,7 +17,7 @@ namespace {
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 constexpr int VF_THREADS = 256;
-constexpr int VF_TEAM = 16;
+constexpr int VF_TEAM = 8;
 constexpr int VF_OUT = 1024;  // staged kept pairs per workgroup
 constexpr int NUM_XCD = 8;
 
@@ -41,51 +47,65 @@ __global__ __launch_bounds__(VF_THREADS) void k_verify(const float* __restrict__
     // every lane of a workgroup runs the same number of iterations, so
     // wave_append and the flushes are reached uniformly
     const int64_t rounds = (hi - lo + nteams - 1) / nteams;
+    uint2 nxt = make_uint2(0u, 0u);
+    if (lo + team < hi) nxt = *reinterpret_cast<const uint2*>(pairs + 2 * (lo + team));
     for (int64_t it = 0; it < rounds; ++it) {
         const int64_t q = lo + team + it * nteams;
         bool live = q < hi;
-        uint32_t i = 0, j = 0;
-        if (live) {
-            const uint2 pr = *reinterpret_cast<const uint2*>(pairs + 2 * q);
-            i = pr.x;
-            j = pr.y;
-            if ((int64_t)i >= n || (int64_t)j >= n) {
-                if (tl == 0) atomicAdd(bad, 1u);
-                live = false;
-            }
+        const uint32_t i = nxt.x, j = nxt.y;
+        if (q + nteams < hi) nxt = *reinterpret_cast<const uint2*>(pairs + 2 * (q + nteams));
+        if (live && ((int64_t)i >= n || (int64_t)j >= n)) {
+            if (tl == 0) atomicAdd(bad, 1u);
+            live = false;
         }
         float a0 = 0.f, a1 = 0.f, a2 = 0.f;
+        auto acc = [&](float u, float v) {
+            if (METRIC == MSM_EUCLIDEAN) {
+                const float e = u - v;
+                a0 = fmaf(e, e, a0);
+            } else {
+                a0 = fmaf(u, v, a0);
+                a1 = fmaf(u, u, a1);
+                a2 = fmaf(v, v, a2);
+            }
+        };
         if (live) {
             const float* xi = X + (int64_t)i * ldx;
             const float* xj = X + (int64_t)j * ldx;
             if (VEC4) {
-                for (int t = tl * 4; t < d; t += VF_TEAM * 4) {
+                constexpr int STEP = VF_TEAM * 4;
+                int t = tl * 4;
+                for (; t + 3 * STEP < d; t += 4 * STEP) {
+                    floatx4 u[4], v[4];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        u[r] = *reinterpret_cast<const floatx4*>(xi + t + r * STEP);
+                        v[r] = *reinterpret_cast<const floatx4*>(xj + t + r * STEP);
+                    }
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) acc(u[r][c], v[r][c]);
+                }
+                for (; t < d; t += STEP) {
                     const floatx4 u = *reinterpret_cast<const floatx4*>(xi + t);
                     const floatx4 v = *reinterpret_cast<const floatx4*>(xj + t);
 #pragma unroll
-                    for (int c = 0; c < 4; ++c) {
-                        if (METRIC == MSM_EUCLIDEAN) {
-                            const float e = u[c] - v[c];
-                            a0 = fmaf(e, e, a0);
-                        } else {
-                            a0 = fmaf(u[c], v[c], a0);
-                            a1 = fmaf(u[c], u[c], a1);
-                            a2 = fmaf(v[c], v[c], a2);
-                        }
-                    }
+                    for (int c = 0; c < 4; ++c) acc(u[c], v[c]);
                 }
             } else {
-                for (int t = tl; t < d; t += VF_TEAM) {
-                    const float u = xi[t], v = xj[t];
-                    if (METRIC == MSM_EUCLIDEAN) {
-                        const float e = u - v;
-                        a0 = fmaf(e, e, a0);
-                    } else {
-                        a0 = fmaf(u, v, a0);
-                        a1 = fmaf(u, u, a1);
-                        a2 = fmaf(v, v, a2);
+                int t = tl;
+                for (; t + 3 * VF_TEAM < d; t += 4 * VF_TEAM) {
+                    float u[4], v[4];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        u[r] = xi[t + r * VF_TEAM];
+                        v[r] = xj[t + r * VF_TEAM];
                     }
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) acc(u[r], v[r]);
                 }
+                for (; t < d; t += VF_TEAM) acc(xi[t], xj[t]);
             }
         }
 #pragma unroll

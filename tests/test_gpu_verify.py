@@ -96,3 +96,17 @@ def test_verify_capacity_and_invalid(msm, ctx):
     with pytest.raises(msm.MSMError) as e:
         msm.msm_verify(ctx, X, P, 7, 0.1)
     assert e.value.status == msm.MSM_E_INVALID
+
+
+
+def test_verify_mixed_scales(msm, ctx):
+    """Rows far from the origin (norms near 800), and rows scaled by 1e-20
+    (tiny distances among themselves) and by 1e20 (squares beyond FP32:
+    every pair with them is far)."""
+    rng = np.random.default_rng(12)
+    n, d = 2000, 64
+    X = (100.0 + 0.05 * rng.standard_normal((n, d))).astype(np.float32)
+    X[::50] *= np.float32(1e-20)
+    X[1::50] *= np.float32(1e20)
+    kept, _ = check(msm, ctx, X, _all_pairs(n), O.EUCLIDEAN, 0.45)
+    assert kept > 0
