@@ -78,15 +78,13 @@ def copy_calibration(nbytes, reps=3):
     print(json.dumps({"copy_bytes": n * 4, "reps": reps}), flush=True)
 
 
-def algorithmic(kernel, w, n, C, mH, mE, W, screened=False):
+def algorithmic(kernel, w, n, C, mH, mE, W):
     """(amount, unit, bound) of algorithmic work per launch of a kernel.
 
     Units per launch: a launch of the partition and bucket kernels covers n
     points under each of the C groupings (C(k, h) combinations of masked
     blocks, or the hierarchical groupings that replace them); k_verify covers the mH
-    candidate pairs and the n rows (BF16 copies when `screened`, the
-    verification having first rounded the rows with k_rows_bf16);
-    k_project_f32 the n x d x ell products.
+    candidate pairs and the n rows; k_project_f32 the n x d x ell products.
     """
     sb = 8 * W  # bytes of one string
     if kernel == "k_project_f32":
@@ -102,10 +100,7 @@ def algorithmic(kernel, w, n, C, mH, mE, W, screened=False):
         # compulsory traffic: candidate pairs in, kept pairs out, each row
         # of X once (the two rows of every candidate are re-read through the
         # caches, not from HBM)
-        row = 2 * ((w.d + 7) // 8 * 8) + 4 if screened else 4 * w.d
-        return (mH * 8 + mE * 8 + n * row) / 1e9, "GB/s", "hbm"
-    if kernel == "k_rows_bf16":
-        return n * (4 * w.d + 2 * ((w.d + 7) // 8 * 8) + 4) / 1e9, "GB/s", "hbm"
+        return (mH * 8 + mE * 8 + n * 4 * w.d) / 1e9, "GB/s", "hbm"
     return None
 
 
@@ -316,8 +311,7 @@ def roofline_of(res, w, n, W, tag):
     names the workload variant for the stored traffic measurement."""
     phase = res["phase"]
     dom = max(phase, key=lambda k: phase[k]["ms_per_step"])
-    alg = algorithmic(dom, w, n, res["combinations"], res["hamming_pairs"], res["eps_pairs"], W,
-                      screened="k_rows_bf16" in phase)
+    alg = algorithmic(dom, w, n, res["combinations"], res["hamming_pairs"], res["eps_pairs"], W)
     if alg is None:
         return {"kernel": dom, "bound": None, "achieved": None, "peak": None, "unit": None, "frac": None,
                 "traffic": None}
