@@ -166,7 +166,7 @@ msm_status set_config(msm_batch& b, const Config& c)
 template <int W, int DIGIT>
 void launch_bucket(const Params& p, const BatchArgs& ba, int NB, int cc, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_bucket<W, DIGIT, true, BK_THREADS, false, BK_MAXB>), dim3((NB + ba.group - 1) / ba.group, cc),
+    hipLaunchKernelGGL((k_bucket<W, DIGIT, true, BK_THREADS, false, BK_MAXB, 0, false>), dim3((NB + ba.group - 1) / ba.group, cc),
                        dim3(BK_THREADS), 0, s, p, ba);
 }
 
@@ -242,7 +242,7 @@ msm_status enqueue_enumerate(msm_batch& b, int64_t* m_dev, hipStream_t s, bool t
             const uint32_t ovf_cap = (uint32_t)cc * (uint32_t)b.NB;
             p.list_cap = ovf_cap;
             if (prof) kt.reset(new msm::KernelTimer(ctx, s, "k_bucket_large_batch"));
-            hipLaunchKernelGGL((k_bucket<W, BK_DIGIT_L, true, LARGE_THREADS, true, large_maxb<W>()>),
+            hipLaunchKernelGGL((k_bucket<W, BK_DIGIT_L, true, LARGE_THREADS, true, large_maxb<W>(), 0, false>),
                                dim3((unsigned)std::min<uint32_t>(ovf_cap, (uint32_t)big_grid)),
                                dim3(LARGE_THREADS), 0, s, p, ba);
             kt.reset();

@@ -5,6 +5,41 @@
 
 namespace {
 
+// The bucket kernel instantiated for the grouping mode hm (0: one grouping
+// per combination; hierarchical: 8, 16 or 32 for blocks of that many
+// characters, 1 for other layouts; GT when the family bitmaps over 2^k
+// difference sets are too large for LDS): the first pass, or (large) the
+// second pass over buckets above the first pass's capacity.
+template <int W, int HM, bool GT>
+void launch_bucket_mode(bool large, dim3 grid, hipStream_t stream, const Params& p)
+{
+    if (large)
+        hipLaunchKernelGGL((k_bucket<W, BK_DIGIT_L, false, LARGE_THREADS, true, large_maxb<W>(), HM, GT>), grid,
+                           dim3(LARGE_THREADS), 0, stream, p, BatchArgs{});
+    else
+        hipLaunchKernelGGL((k_bucket<W, BK_DIGIT, false, BK_THREADS, false, BK_MAXB, HM, GT>), grid,
+                           dim3(BK_THREADS), 0, stream, p, BatchArgs{});
+}
+
+template <int W, bool GT>
+void launch_bucket_hier(int hm, bool large, dim3 grid, hipStream_t stream, const Params& p)
+{
+    switch (hm) {
+    case 8: launch_bucket_mode<W, 8, GT>(large, grid, stream, p); break;
+    case 16: launch_bucket_mode<W, 16, GT>(large, grid, stream, p); break;
+    case 32: launch_bucket_mode<W, 32, GT>(large, grid, stream, p); break;
+    default: launch_bucket_mode<W, 1, GT>(large, grid, stream, p); break;
+    }
+}
+
+template <int W>
+void launch_bucket(int hm, bool large, dim3 grid, hipStream_t stream, const Params& p)
+{
+    if (hm == 0) launch_bucket_mode<W, 0, false>(large, grid, stream, p);
+    else if (p.k <= DT_LDS_K) launch_bucket_hier<W, false>(hm, large, grid, stream, p);
+    else launch_bucket_hier<W, true>(hm, large, grid, stream, p);
+}
+
 template <int W>
 msm_status run_enumerate(msm_ctx* ctx, const uint64_t* S, int64_t n, int ell, int Q, int k, int h,
                          uint32_t* pairs, int64_t cap, int64_t* m_out, hipStream_t stream)
@@ -174,6 +209,7 @@ msm_status run_enumerate(msm_ctx* ctx, const uint64_t* S, int64_t n, int ell, in
     p.hier = hier ? 1 : 0;
     p.fam = hier ? d_fam : nullptr;
     p.dtab = hier ? d_dtab : nullptr;
+    const int hm = hier ? (p.dL ? p.dL : 1) : 0;
     ctx->last_groupings = C;
     ctx->last_jblocks = hier ? jsel : 0;
 
@@ -204,8 +240,7 @@ msm_status run_enumerate(msm_ctx* ctx, const uint64_t* S, int64_t n, int ell, in
         }
         {
             msm::KernelTimer kt(ctx, stream, "k_bucket");
-            hipLaunchKernelGGL((k_bucket<W, BK_DIGIT, false, BK_THREADS, false, BK_MAXB>), dim3((nb + BK_GROUP - 1) / BK_GROUP, cc),
-                               dim3(BK_THREADS), 0, stream, p, BatchArgs{});
+            launch_bucket<W>(hm, false, dim3((nb + BK_GROUP - 1) / BK_GROUP, cc), stream, p);
         }
         MSM_HIP(ctx, hipGetLastError());
         MSM_HIP(ctx, hipMemcpyAsync(ctx->host_words, d_ovfc, sizeof(uint32_t), hipMemcpyDeviceToHost, stream));
@@ -218,8 +253,7 @@ msm_status run_enumerate(msm_ctx* ctx, const uint64_t* S, int64_t n, int ell, in
             p.list_cap = (uint32_t)cc * (uint32_t)nb;
             {
                 msm::KernelTimer kt(ctx, stream, "k_bucket_large");
-                hipLaunchKernelGGL((k_bucket<W, BK_DIGIT_L, false, LARGE_THREADS, true, large_maxb<W>()>), dim3(nlarge),
-                                   dim3(LARGE_THREADS), 0, stream, p, BatchArgs{});
+                launch_bucket<W>(hm, true, dim3(nlarge), stream, p);
             }
             MSM_HIP(ctx, hipGetLastError());
             MSM_HIP(ctx, hipMemcpyAsync(ctx->host_words, d_ovfc + 1, sizeof(uint32_t), hipMemcpyDeviceToHost,

@@ -446,8 +446,10 @@ __device__ __forceinline__ bool pair_ok(const uint64_t* a, const uint64_t* b, co
 
 // The same test, branch-free, with the masks of the first MAXHI blocks of
 // `hi` held in registers (hm). Combinations with more blocks in `hi` finish
-// with a loop over the block masks in LDS.
-template <int W>
+// with a loop over the block masks in LDS. HM is 0 for one grouping per
+// combination, else the hierarchical block layout (see diff_blocks_of); GT
+// reads the family bitmap from global memory (k > DT_LDS_K), else from LDS.
+template <int W, int HM, bool GT>
 __device__ __forceinline__ bool pair_ok_fast(const uint64_t* a, const uint64_t* b, const Params& p,
                                              const uint64_t (&keep)[W], const uint64_t (&hm)[MAXHI][W], int nhi,
                                              uint64_t hi_rest, const uint32_t* dtabL, const uint32_t* dtabG,
@@ -463,12 +465,14 @@ __device__ __forceinline__ bool pair_ok_fast(const uint64_t* a, const uint64_t* 
         outside |= x[w] & keep[w];
     }
     bool ok = (ham <= p.h) & (outside == 0);
-    if (p.hier) {
+    if constexpr (HM != 0) {
         // the pair's difference set must be in the partition's family
         uint32_t D = 0;
-        if (p.dL) D = diff_blocks<W>(x, p);
-        else if (ok) D = diff_blocks<W>(x, p);
-        const uint32_t word = p.k <= DT_LDS_K ? dtabL[D >> 5] : dtabG[D >> 5];
+        if constexpr (HM != 1) D = diff_blocks_of<W, HM>(x, p);
+        else if (ok) D = diff_blocks_of<W, 1>(x, p);
+        uint32_t word;
+        if constexpr (GT) word = dtabG[D >> 5];
+        else word = dtabL[D >> 5];
         return ok & (((word >> (D & 31)) & 1u) != 0u);
     }
 #pragma unroll
@@ -534,11 +538,13 @@ __device__ __forceinline__ int block_of(const Params& p, int c)
 // inside the field), and the top bits are then gathered into consecutive
 // bits. Other layouts visit the set characters one by one; the caller does
 // that only for pairs within distance h, so at most h of them.
-template <int W>
-__device__ __forceinline__ uint32_t diff_blocks(const uint64_t (&x)[W], const Params& p)
+// HM is the block layout: 8, 16 or 32 for blocks of that many characters,
+// 1 for any other layout.
+template <int W, int HM>
+__device__ __forceinline__ uint32_t diff_blocks_of(const uint64_t (&x)[W], const Params& p)
 {
     uint32_t D = 0;
-    if (p.dL == 16) {
+    if constexpr (HM == 16) {
 #pragma unroll
         for (int w = 0; w < W; ++w)
 #pragma unroll
@@ -547,7 +553,7 @@ __device__ __forceinline__ uint32_t diff_blocks(const uint64_t (&x)[W], const Pa
                 const uint32_t t = (((v & 0x7FFF7FFFu) + 0x7FFF7FFFu) | v) & 0x80008000u;
                 D |= (((t >> 15) & 1u) | (t >> 30)) << (4 * w + 2 * hf);
             }
-    } else if (p.dL == 8) {
+    } else if constexpr (HM == 8) {
 #pragma unroll
         for (int w = 0; w < W; ++w)
 #pragma unroll
@@ -558,7 +564,7 @@ __device__ __forceinline__ uint32_t diff_blocks(const uint64_t (&x)[W], const Pa
                 // them at 21..24 with no two partial products overlapping
                 D |= ((((t >> 7) * 0x00204081u) >> 21) & 0xFu) << (8 * w + 4 * hf);
             }
-    } else if (p.dL == 32) {
+    } else if constexpr (HM == 32) {
 #pragma unroll
         for (int w = 0; w < W; ++w) {
             D |= (uint32_t)((uint32_t)x[w] != 0u) << (2 * w);
@@ -575,6 +581,15 @@ __device__ __forceinline__ uint32_t diff_blocks(const uint64_t (&x)[W], const Pa
         }
     }
     return D;
+}
+
+template <int W>
+__device__ __forceinline__ uint32_t diff_blocks(const uint64_t (&x)[W], const Params& p)
+{
+    if (p.dL == 16) return diff_blocks_of<W, 16>(x, p);
+    if (p.dL == 8) return diff_blocks_of<W, 8>(x, p);
+    if (p.dL == 32) return diff_blocks_of<W, 32>(x, p);
+    return diff_blocks_of<W, 1>(x, p);
 }
 
 __device__ __forceinline__ bool in_family(const uint32_t* tab, uint32_t D)
@@ -604,10 +619,11 @@ __device__ __forceinline__ bool in_family(const uint32_t* tab, uint32_t D)
 // found too large), and lists the ones too large for it in p.ovf2.
 // The first pass for W <= 2 fits four workgroups per CU in LDS; its
 // register budget is held to the matching four waves per SIMD.
-template <int W, int DIGIT, bool BATCH, int TH, bool LIST, int MAXB>
+template <int W, int DIGIT, bool BATCH, int TH, bool LIST, int MAXB, int HM, bool GT>
 __global__ __launch_bounds__(TH, (TH == BK_THREADS && W <= 2 && DIGIT <= 10) ? 4 : 1) void k_bucket(Params p,
                                                                                                    BatchArgs ba)
 {
+    constexpr bool HIER = HM != 0;
     constexpr int BINS = 1 << DIGIT;
     constexpr int CAP = TH * MAXB;
     // hist holds the digit counts, then (for bins that form runs) the run's
@@ -752,7 +768,7 @@ __global__ __launch_bounds__(TH, (TH == BK_THREADS && W <= 2 && DIGIT <= 10) ? 4
             }
         }
         __syncthreads();  // LDS of the previous bucket is free, hist is zero
-        if (p.hier && p.k <= DT_LDS_K && tab_c != cl) {
+        if (HIER && !GT && tab_c != cl) {
             // the partition's bitmap, read only after the histogram's barrier
             const int words = max(1, (1 << p.k) >> 5);
             for (int e = threadIdx.x; e < words; e += TH) dtabL[e] = dtabG[e];
@@ -851,14 +867,14 @@ __global__ __launch_bounds__(TH, (TH == BK_THREADS && W <= 2 && DIGIT <= 10) ? 4
 #pragma unroll
         for (int b = 0; b < MAXB; ++b) {
             if (b * TH < m && rank[b] != 0xFFFFFFFFu) {
-                if ((hi || p.hier) && c[b] >= 2 && rank[b] > 0) {
+                if ((hi || HIER) && c[b] >= 2 && rank[b] > 0) {
                     const uint32_t first = rfirst[b];
                     const uint32_t q = first + rank[b];
                     uint64_t x[W];
 #pragma unroll
                     for (int w = 0; w < W; ++w) x[w] = sl[q * W + w] ^ sl[first * W + w];
                     uint64_t bits = 0;
-                    if (p.hier) {
+                    if constexpr (HIER) {
                         // every block in which the member differs from the first
                         for (int blk = 0; blk < p.k; ++blk) {
                             uint64_t any = 0;
@@ -891,7 +907,7 @@ __global__ __launch_bounds__(TH, (TH == BK_THREADS && W <= 2 && DIGIT <= 10) ? 4
             }
         }
         if (nruns == 0) continue;
-        if (hi || p.hier) __syncthreads();
+        if (hi || HIER) __syncthreads();
 
         // Each run claims its pairs, unless it cannot hold a pair to write:
         // a pair is written only if it differs in every block of `hi`, so a
@@ -899,7 +915,7 @@ __global__ __launch_bounds__(TH, (TH == BK_THREADS && W <= 2 && DIGIT <= 10) ? 4
         for (uint32_t r = threadIdx.x; r < nruns; r += TH) {
             const int s0 = runS[r], L = runL[r];
             bool live;
-            if (p.hier) {
+            if constexpr (HIER) {
                 // some difference set of the family fits in the run's varying blocks
                 const uint64_t v = runBlk[r];
                 live = nfam < 0;  // no family stored: keep every run
@@ -978,7 +994,7 @@ __global__ __launch_bounds__(TH, (TH == BK_THREADS && W <= 2 && DIGIT <= 10) ? 4
                 if (q >= cpl) break;
                 const bool live = t + q < P;
                 const bool ok =
-                    live & pair_ok_fast<W>(&sl[pa[q] * W], &sl[pb[q] * W], p, keep, hm, nhi, hi_rest, dtabL,
+                    live & pair_ok_fast<W, HM, GT>(&sl[pa[q] * W], &sl[pb[q] * W], p, keep, hm, nhi, hi_rest, dtabL,
                                                   dtabG, bmL);
                 okbits |= (uint32_t)ok << q;
             }
