@@ -46,7 +46,7 @@ def measured_traffic(kernel, workload):
     """HBM bytes per launch of `kernel` on `workload` from the stored
     rocprofv3 counter runs (FETCH_SIZE and WRITE_SIZE, each scaled by the
     same counter's reading for a copy of known size), or None when there is
-    no such measurement or the kernel's source has changed since."""
+    no such measurement or one of the kernel's sources has changed since."""
     import hashlib
     try:
         with open(TRAFFIC_FILE) as f:
@@ -56,10 +56,14 @@ def measured_traffic(kernel, workload):
     for e in entries:
         if e.get("kernel") != kernel or e.get("workload") != workload:
             continue
+        srcs, shas = e["source"], e["sha256"]
+        if isinstance(srcs, str):
+            srcs, shas = [srcs], [shas]
         try:
-            with open(os.path.join(ROOT, e["source"]), "rb") as f:
-                if hashlib.sha256(f.read()).hexdigest() != e["sha256"]:
-                    return None
+            for src, sha in zip(srcs, shas):
+                with open(os.path.join(ROOT, src), "rb") as f:
+                    if hashlib.sha256(f.read()).hexdigest() != sha:
+                        return None
         except OSError:
             return None
         return e["bytes_per_launch"]
