@@ -18,6 +18,7 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 constexpr int VF_THREADS = 256;
 constexpr int VF_TEAM = 8;
+constexpr int VF_PP = 2;     // consecutive pairs a team takes per iteration
 constexpr int VF_OUT = 1024;  // staged kept pairs per workgroup
 constexpr int NUM_XCD = 8;
 
@@ -45,88 +46,122 @@ __global__ __launch_bounds__(VF_THREADS) void k_verify(const float* __restrict__
     const int64_t team = ((int64_t)(blockIdx.x / NUM_XCD) * VF_THREADS + threadIdx.x) / VF_TEAM;
     const int64_t nteams = (per_die * VF_THREADS) / VF_TEAM;
     // every lane of a workgroup runs the same number of iterations, so
-    // wave_append and the flushes are reached uniformly
-    const int64_t rounds = (hi - lo + nteams - 1) / nteams;
-    uint2 nxt = make_uint2(0u, 0u);
-    if (lo + team < hi) nxt = *reinterpret_cast<const uint2*>(pairs + 2 * (lo + team));
+    // wave_append and the flushes are reached uniformly; a team takes VF_PP
+    // consecutive pairs per iteration
+    const int64_t span = nteams * VF_PP;
+    const int64_t rounds = (hi - lo + span - 1) / span;
+    uint2 nxt[VF_PP];
+#pragma unroll
+    for (int pp = 0; pp < VF_PP; ++pp) {
+        const int64_t q = lo + team * VF_PP + pp;
+        nxt[pp] = q < hi ? *reinterpret_cast<const uint2*>(pairs + 2 * q) : make_uint2(0u, 0u);
+    }
     for (int64_t it = 0; it < rounds; ++it) {
-        const int64_t q = lo + team + it * nteams;
-        bool live = q < hi;
-        const uint32_t i = nxt.x, j = nxt.y;
-        if (q + nteams < hi) nxt = *reinterpret_cast<const uint2*>(pairs + 2 * (q + nteams));
-        if (live && ((int64_t)i >= n || (int64_t)j >= n)) {
-            if (tl == 0) atomicAdd(bad, 1u);
-            live = false;
+        const int64_t q0 = lo + (team + it * nteams) * VF_PP;
+        bool live[VF_PP];
+        uint32_t pi[VF_PP], pj[VF_PP];
+        const float* xi[VF_PP];
+        const float* xj[VF_PP];
+#pragma unroll
+        for (int pp = 0; pp < VF_PP; ++pp) {
+            live[pp] = q0 + pp < hi;
+            pi[pp] = nxt[pp].x;
+            pj[pp] = nxt[pp].y;
+            if (q0 + span + pp < hi) nxt[pp] = *reinterpret_cast<const uint2*>(pairs + 2 * (q0 + span + pp));
+            if (live[pp] && ((int64_t)pi[pp] >= n || (int64_t)pj[pp] >= n)) {
+                if (tl == 0) atomicAdd(bad, 1u);
+                live[pp] = false;
+            }
+            // rows of a dead slot point at row 0 and are not read
+            xi[pp] = X + (live[pp] ? (int64_t)pi[pp] * ldx : 0);
+            xj[pp] = X + (live[pp] ? (int64_t)pj[pp] * ldx : 0);
         }
-        float a0 = 0.f, a1 = 0.f, a2 = 0.f;
-        auto acc = [&](float u, float v) {
+        float a0[VF_PP], a1[VF_PP], a2[VF_PP];
+#pragma unroll
+        for (int pp = 0; pp < VF_PP; ++pp) a0[pp] = a1[pp] = a2[pp] = 0.f;
+        auto acc = [&](int pp, float u, float v) {
             if (METRIC == MSM_EUCLIDEAN) {
                 const float e = u - v;
-                a0 = fmaf(e, e, a0);
+                a0[pp] = fmaf(e, e, a0[pp]);
             } else {
-                a0 = fmaf(u, v, a0);
-                a1 = fmaf(u, u, a1);
-                a2 = fmaf(v, v, a2);
+                a0[pp] = fmaf(u, v, a0[pp]);
+                a1[pp] = fmaf(u, u, a1[pp]);
+                a2[pp] = fmaf(v, v, a2[pp]);
             }
         };
-        if (live) {
-            const float* xi = X + (int64_t)i * ldx;
-            const float* xj = X + (int64_t)j * ldx;
-            if (VEC4) {
-                constexpr int STEP = VF_TEAM * 4;
-                int t = tl * 4;
-                for (; t + 3 * STEP < d; t += 4 * STEP) {
-                    floatx4 u[4], v[4];
+        if (VEC4) {
+            constexpr int STEP = VF_TEAM * 4;
+            constexpr int UN = 4 / VF_PP;  // row steps per pair in flight
+            int t = tl * 4;
+            for (; t + (UN - 1) * STEP < d; t += UN * STEP) {
+                floatx4 u[VF_PP][UN], v[VF_PP][UN];
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        u[r] = *reinterpret_cast<const floatx4*>(xi + t + r * STEP);
-                        v[r] = *reinterpret_cast<const floatx4*>(xj + t + r * STEP);
+                for (int pp = 0; pp < VF_PP; ++pp)
+#pragma unroll
+                    for (int r = 0; r < UN; ++r) {
+                        const floatx4 z = {0.f, 0.f, 0.f, 0.f};
+                        u[pp][r] = live[pp] ? *reinterpret_cast<const floatx4*>(xi[pp] + t + r * STEP) : z;
+                        v[pp][r] = live[pp] ? *reinterpret_cast<const floatx4*>(xj[pp] + t + r * STEP) : z;
                     }
 #pragma unroll
-                    for (int r = 0; r < 4; ++r)
+                for (int pp = 0; pp < VF_PP; ++pp)
 #pragma unroll
-                        for (int c = 0; c < 4; ++c) acc(u[r][c], v[r][c]);
-                }
-                for (; t < d; t += STEP) {
-                    const floatx4 u = *reinterpret_cast<const floatx4*>(xi + t);
-                    const floatx4 v = *reinterpret_cast<const floatx4*>(xj + t);
+                    for (int r = 0; r < UN; ++r)
 #pragma unroll
-                    for (int c = 0; c < 4; ++c) acc(u[c], v[c]);
+                        for (int c = 0; c < 4; ++c) acc(pp, u[pp][r][c], v[pp][r][c]);
+            }
+            for (; t < d; t += STEP) {
+#pragma unroll
+                for (int pp = 0; pp < VF_PP; ++pp) {
+                    if (!live[pp]) continue;
+                    const floatx4 u = *reinterpret_cast<const floatx4*>(xi[pp] + t);
+                    const floatx4 v = *reinterpret_cast<const floatx4*>(xj[pp] + t);
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) acc(pp, u[c], v[c]);
                 }
-            } else {
+            }
+        } else {
+#pragma unroll
+            for (int pp = 0; pp < VF_PP; ++pp) {
+                if (!live[pp]) continue;
                 int t = tl;
                 for (; t + 3 * VF_TEAM < d; t += 4 * VF_TEAM) {
                     float u[4], v[4];
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
-                        u[r] = xi[t + r * VF_TEAM];
-                        v[r] = xj[t + r * VF_TEAM];
+                        u[r] = xi[pp][t + r * VF_TEAM];
+                        v[r] = xj[pp][t + r * VF_TEAM];
                     }
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) acc(u[r], v[r]);
+                    for (int r = 0; r < 4; ++r) acc(pp, u[r], v[r]);
                 }
-                for (; t < d; t += VF_TEAM) acc(xi[t], xj[t]);
+                for (; t < d; t += VF_TEAM) acc(pp, xi[pp][t], xj[pp][t]);
             }
         }
 #pragma unroll
-        for (int o = VF_TEAM / 2; o > 0; o >>= 1) {
-            a0 += __shfl_xor(a0, o, 64);
-            if (METRIC == MSM_COSINE) {
-                a1 += __shfl_xor(a1, o, 64);
-                a2 += __shfl_xor(a2, o, 64);
+        for (int pp = 0; pp < VF_PP; ++pp) {
+#pragma unroll
+            for (int o = VF_TEAM / 2; o > 0; o >>= 1) {
+                a0[pp] += __shfl_xor(a0[pp], o, 64);
+                if (METRIC == MSM_COSINE) {
+                    a1[pp] += __shfl_xor(a1[pp], o, 64);
+                    a2[pp] += __shfl_xor(a2[pp], o, 64);
+                }
             }
-        }
-        bool keep = false;
-        if (live && tl == 0) {
-            if (METRIC == MSM_EUCLIDEAN) {
-                keep = a0 <= eps * eps;
-            } else {
-                const float dist = (a1 == 0.f || a2 == 0.f) ? 1.0f : 1.0f - a0 / (sqrtf(a1) * sqrtf(a2));
-                keep = dist <= eps;
+            bool keep = false;
+            if (live[pp] && tl == 0) {
+                if (METRIC == MSM_EUCLIDEAN) {
+                    keep = a0[pp] <= eps * eps;
+                } else {
+                    const float dist = (a1[pp] == 0.f || a2[pp] == 0.f)
+                                           ? 1.0f
+                                           : 1.0f - a0[pp] / (sqrtf(a1[pp]) * sqrtf(a2[pp]));
+                    keep = dist <= eps;
+                }
             }
+            stage.push(keep, pi[pp], pj[pp]);
         }
-        stage.push(keep, i, j);
-        if ((it & 15) == 15) stage.maybe_flush(VF_OUT / 2);
+        if ((it & (16 / VF_PP - 1)) == 16 / VF_PP - 1) stage.maybe_flush(VF_OUT / 2);
     }
     stage.flush();
 }
@@ -168,6 +203,7 @@ extern "C" msm_status msm_verify(msm_ctx* ctx, const float* X, int64_t n, int32_
         return msm::fail(ctx, MSM_E_INVALID, "msm_verify: eps must be finite and >= 0");
     if (m == 0) return MSM_OK;
     if (!X || !pairs) return msm::fail(ctx, MSM_E_INVALID, "msm_verify: NULL X or pairs");
+    if (n == 0) return msm::fail(ctx, MSM_E_INVALID, "msm_verify: %lld pairs index an empty X", (long long)m);
     if (cap > 0 && !out) return msm::fail(ctx, MSM_E_INVALID, "msm_verify: out is NULL with cap > 0");
     if ((reinterpret_cast<uintptr_t>(pairs) & 7) || (out && (reinterpret_cast<uintptr_t>(out) & 7)))
         return msm::fail(ctx, MSM_E_INVALID, "msm_verify: pair buffers must be 8-byte aligned");
@@ -181,8 +217,8 @@ extern "C" msm_status msm_verify(msm_ctx* ctx, const float* X, int64_t n, int32_
     uint32_t* bad = reinterpret_cast<uint32_t*>(counter + 1);
     hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(64), 0, s, counter, 2);
     const bool vec4 = ((reinterpret_cast<uintptr_t>(X) & 15) == 0) && (ldx % 4 == 0) && (d % 4 == 0);
-    const int64_t teams_per_block = VF_THREADS / VF_TEAM;
-    int64_t blocks = (m + teams_per_block - 1) / teams_per_block;
+    const int64_t pairs_per_block = VF_THREADS / VF_TEAM * VF_PP;
+    int64_t blocks = (m + pairs_per_block - 1) / pairs_per_block;
     const int64_t max_blocks = (int64_t)ctx->num_cu * 16;
     if (blocks > max_blocks) blocks = max_blocks;
     blocks = (blocks + NUM_XCD - 1) / NUM_XCD * NUM_XCD;
