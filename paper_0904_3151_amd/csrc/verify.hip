@@ -3,7 +3,7 @@
 // A team of VF_TEAM lanes handles one pair: each lane reads consecutive
 // 16-byte pieces of x_i and x_j (a team covers VF_TEAM * 16 contiguous bytes
 // per row per step), four steps at a time so that eight loads per lane are
-// in flight, accumulates in FP32, and the team reduces with lane shuffles.
+// in flight, accumulates in FP32, and the team reduces with DPP adds.
 // The next pair's indices are fetched while the current pair is computed.
 // The team leaders then append the kept pairs with one atomic per wave.
 //
@@ -21,6 +21,19 @@ constexpr int VF_TEAM = 8;
 constexpr int VF_PP = 2;     // consecutive pairs a team takes per iteration
 constexpr int VF_OUT = 1024;  // staged kept pairs per workgroup
 constexpr int NUM_XCD = 8;
+static_assert(VF_TEAM == 8, "team_sum adds over eight lanes");
+
+// Sum over the eight lanes of a team with DPP adds: lanes xor 1 and xor 2
+// inside each quad, then each lane and its mirror in the half row (lane
+// 7 - l), which pairs the two quads. Every lane ends with the same sum (each
+// step adds the same two values in either order).
+__device__ __forceinline__ float team_sum(float v)
+{
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));  // quad [1,0,3,2]
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, false));  // quad [2,3,0,1]
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x141, 0xF, 0xF, false)); // half mirror
+    return v;
+}
 
 template <int METRIC, bool VEC4>
 __global__ __launch_bounds__(VF_THREADS) void k_verify(const float* __restrict__ X, int64_t n, int d,
@@ -72,7 +85,7 @@ __global__ __launch_bounds__(VF_THREADS) void k_verify(const float* __restrict__
                 if (tl == 0) atomicAdd(bad, 1u);
                 live[pp] = false;
             }
-            // rows of a dead slot point at row 0 and are not read
+            // a dead slot reads row 0 (n >= 1) and its result is dropped
             xi[pp] = X + (live[pp] ? (int64_t)pi[pp] * ldx : 0);
             xj[pp] = X + (live[pp] ? (int64_t)pj[pp] * ldx : 0);
         }
@@ -99,9 +112,8 @@ __global__ __launch_bounds__(VF_THREADS) void k_verify(const float* __restrict__
                 for (int pp = 0; pp < VF_PP; ++pp)
 #pragma unroll
                     for (int r = 0; r < UN; ++r) {
-                        const floatx4 z = {0.f, 0.f, 0.f, 0.f};
-                        u[pp][r] = live[pp] ? *reinterpret_cast<const floatx4*>(xi[pp] + t + r * STEP) : z;
-                        v[pp][r] = live[pp] ? *reinterpret_cast<const floatx4*>(xj[pp] + t + r * STEP) : z;
+                        u[pp][r] = *reinterpret_cast<const floatx4*>(xi[pp] + t + r * STEP);
+                        v[pp][r] = *reinterpret_cast<const floatx4*>(xj[pp] + t + r * STEP);
                     }
 #pragma unroll
                 for (int pp = 0; pp < VF_PP; ++pp)
@@ -113,7 +125,6 @@ __global__ __launch_bounds__(VF_THREADS) void k_verify(const float* __restrict__
             for (; t < d; t += STEP) {
 #pragma unroll
                 for (int pp = 0; pp < VF_PP; ++pp) {
-                    if (!live[pp]) continue;
                     const floatx4 u = *reinterpret_cast<const floatx4*>(xi[pp] + t);
                     const floatx4 v = *reinterpret_cast<const floatx4*>(xj[pp] + t);
 #pragma unroll
@@ -123,7 +134,6 @@ __global__ __launch_bounds__(VF_THREADS) void k_verify(const float* __restrict__
         } else {
 #pragma unroll
             for (int pp = 0; pp < VF_PP; ++pp) {
-                if (!live[pp]) continue;
                 int t = tl;
                 for (; t + 3 * VF_TEAM < d; t += 4 * VF_TEAM) {
                     float u[4], v[4];
@@ -140,13 +150,10 @@ __global__ __launch_bounds__(VF_THREADS) void k_verify(const float* __restrict__
         }
 #pragma unroll
         for (int pp = 0; pp < VF_PP; ++pp) {
-#pragma unroll
-            for (int o = VF_TEAM / 2; o > 0; o >>= 1) {
-                a0[pp] += __shfl_xor(a0[pp], o, 64);
-                if (METRIC == MSM_COSINE) {
-                    a1[pp] += __shfl_xor(a1[pp], o, 64);
-                    a2[pp] += __shfl_xor(a2[pp], o, 64);
-                }
+            a0[pp] = team_sum(a0[pp]);
+            if (METRIC == MSM_COSINE) {
+                a1[pp] = team_sum(a1[pp]);
+                a2[pp] = team_sum(a2[pp]);
             }
             bool keep = false;
             if (live[pp] && tl == 0) {
