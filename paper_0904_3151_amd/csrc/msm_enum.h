@@ -449,20 +449,23 @@ __device__ __forceinline__ bool pair_ok(const uint64_t* a, const uint64_t* b, co
 // with a loop over the block masks in LDS. HM is 0 for one grouping per
 // combination, else the hierarchical block layout (see diff_blocks_of); GT
 // reads the family bitmap from global memory (k > DT_LDS_K), else from LDS.
+// A hierarchical partition keeps every block outside its family's union, so
+// the bitmap alone also rejects pairs that differ in a kept block.
 template <int W, int HM, bool GT>
 __device__ __forceinline__ bool pair_ok_fast(const uint64_t* a, const uint64_t* b, const Params& p,
                                              const uint64_t (&keep)[W], const uint64_t (&hm)[MAXHI][W], int nhi,
                                              uint64_t hi_rest, const uint32_t* dtabL, const uint32_t* dtabG,
                                              const uint64_t* __restrict__ bmL)
 {
+    // the strings in LDS are already cut to ell characters
     uint64_t x[W];
     int ham = 0;
     uint64_t outside = 0;
 #pragma unroll
     for (int w = 0; w < W; ++w) {
-        x[w] = (a[w] ^ b[w]) & p.valid[w];
+        x[w] = a[w] ^ b[w];
         ham += __popcll(x[w]);
-        outside |= x[w] & keep[w];
+        if constexpr (HM == 0) outside |= x[w] & keep[w];
     }
     bool ok = (ham <= p.h) & (outside == 0);
     if constexpr (HM != 0) {
@@ -545,14 +548,18 @@ __device__ __forceinline__ uint32_t diff_blocks_of(const uint64_t (&x)[W], const
 {
     uint32_t D = 0;
     if constexpr (HM == 16) {
+        // min(field, 1) on both 16-bit halves at once (one packed VALU op;
+        // left to itself the compiler tests each field with a compare and a
+        // select); then bit 0 and bit 16 of each half-word (the second one
+        // shifted up by two) are the word's four block bits
 #pragma unroll
-        for (int w = 0; w < W; ++w)
-#pragma unroll
-            for (int hf = 0; hf < 2; ++hf) {
-                const uint32_t v = (uint32_t)(x[w] >> (32 * hf));
-                const uint32_t t = (((v & 0x7FFF7FFFu) + 0x7FFF7FFFu) | v) & 0x80008000u;
-                D |= (((t >> 15) & 1u) | (t >> 30)) << (4 * w + 2 * hf);
-            }
+        for (int w = 0; w < W; ++w) {
+            uint32_t f0, f1;
+            asm("v_pk_min_u16 %0, %1, %2" : "=v"(f0) : "v"((uint32_t)x[w]), "s"(0x10001u));
+            asm("v_pk_min_u16 %0, %1, %2" : "=v"(f1) : "v"((uint32_t)(x[w] >> 32)), "s"(0x10001u));
+            const uint32_t c = f0 | (f1 << 2);  // bits 0, 2, 16, 18
+            D |= ((c | (c >> 15)) & 0xFu) << (4 * w);
+        }
     } else if constexpr (HM == 8) {
 #pragma unroll
         for (int w = 0; w < W; ++w)
@@ -856,7 +863,7 @@ __global__ __launch_bounds__(TH, (TH == BK_THREADS && W <= 2 && DIGIT <= 10) ? 4
                 const uint32_t q = rfirst[b] + rank[b];
                 idxB[q] = (uint32_t)cur[b];
 #pragma unroll
-                for (int w = 0; w < W; ++w) sl[q * W + w] = sreg[b][w];
+                for (int w = 0; w < W; ++w) sl[q * W + w] = sreg[b][w] & p.valid[w];
             }
         }
         const uint32_t nruns = (uint32_t)(claimRun >> 32);
@@ -988,15 +995,38 @@ __global__ __launch_bounds__(TH, (TH == BK_THREADS && W <= 2 && DIGIT <= 10) ? 4
                 }
             }
             uint32_t okbits = 0;
-            // point indices are read from LDS only for the pairs that pass
+            // the next candidate's strings are requested before the current
+            // one is tested; point indices are read from LDS only for the
+            // pairs that pass
+            uint64_t sa[W], sb[W];
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+                sa[w] = sl[pa[0] * W + w];
+                sb[w] = sl[pb[0] * W + w];
+            }
 #pragma unroll
             for (int q = 0; q < BK_PAIR_CHUNK; ++q) {
                 if (q >= cpl) break;
+                uint64_t na[W], nb[W];
+                const bool more = q + 1 < BK_PAIR_CHUNK && q + 1 < cpl;
+                if (more) {
+#pragma unroll
+                    for (int w = 0; w < W; ++w) {
+                        na[w] = sl[pa[q + 1 < BK_PAIR_CHUNK ? q + 1 : q] * W + w];
+                        nb[w] = sl[pb[q + 1 < BK_PAIR_CHUNK ? q + 1 : q] * W + w];
+                    }
+                }
                 const bool live = t + q < P;
                 const bool ok =
-                    live & pair_ok_fast<W, HM, GT>(&sl[pa[q] * W], &sl[pb[q] * W], p, keep, hm, nhi, hi_rest, dtabL,
-                                                  dtabG, bmL);
+                    live & pair_ok_fast<W, HM, GT>(sa, sb, p, keep, hm, nhi, hi_rest, dtabL, dtabG, bmL);
                 okbits |= (uint32_t)ok << q;
+                if (more) {
+#pragma unroll
+                    for (int w = 0; w < W; ++w) {
+                        sa[w] = na[w];
+                        sb[w] = nb[w];
+                    }
+                }
             }
             if (p.rep > 0 && okbits) {
 #pragma unroll
