@@ -79,9 +79,10 @@ __device__ __forceinline__ void project_tile(const float* __restrict__ X, int64_
             __syncthreads();
         }
         const int kcn = min(kt_chunks, (d - k0 + 15) / 16);
-        for (int kc = 0; kc < kcn; ++kc) {
+        // X values of chunk kc; the next chunk's are requested before this
+        // chunk's products
+        auto load_a = [&](int kc, floatx4 (&a)[RB]) {
             const int kbase = k0 + kc * 16 + 4 * g;
-            floatx4 a[RB];
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb) {
                 const int64_t row = row_w + rb * 16 + r16;
@@ -98,6 +99,14 @@ __device__ __forceinline__ void project_tile(const float* __restrict__ X, int64_
                 }
                 a[rb] = v;
             }
+        };
+        floatx4 an[RB];
+        if (kcn > 0) load_a(0, an);
+        for (int kc = 0; kc < kcn; ++kc) {
+            floatx4 a[RB];
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) a[rb] = an[rb];
+            if (kc + 1 < kcn) load_a(kc + 1, an);
             floatx4 b[NCB];
 #pragma unroll
             for (int cb = 0; cb < NCB; ++cb) b[cb] = Rl[(kc * NCB + cb) * 64 + lane];
