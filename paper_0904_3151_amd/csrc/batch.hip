@@ -248,8 +248,8 @@ msm_status enqueue_enumerate(msm_batch& b, int64_t* m_dev, hipStream_t s, bool t
             kt.reset();
             if (prof) kt.reset(new msm::KernelTimer(ctx, s, "k_big_batch"));
             hipLaunchKernelGGL(k_ovf_prefix, dim3(1), dim3(1024), 0, s, b.d_ovf2, b.d_ovfc + 1, ovf_cap, b.d_tile0);
-            hipLaunchKernelGGL((k_big_batch<W>), dim3(big_grid), dim3(BIG_TILE), 0, s, p, ba, b.d_ovf2, b.d_ovfc + 1,
-                               ovf_cap, b.d_tile0, b.d_work);
+            hipLaunchKernelGGL((k_big<W, true>), dim3(big_grid), dim3(BIG_TILE), 0, s, p, ba, b.d_ovf2, b.d_ovfc + 1,
+                               ovf_cap, b.d_tile0, b.d_work, nullptr);
         }
         MSM_HIP(ctx, hipGetLastError());
     }

@@ -3,6 +3,8 @@
 // method and its kernels are described in msm_enum.h.
 #include "msm_enum.h"
 
+#include <cstring>
+
 namespace {
 
 // The bucket kernel instantiated for the grouping mode hm (0: one grouping
@@ -74,18 +76,22 @@ msm_status run_enumerate(msm_ctx* ctx, const uint64_t* S, int64_t n, int ell, in
     int Cg = (int)std::max<size_t>(1, std::min<size_t>((size_t)Cmax, budget / per_combo));
     Cg = std::min(Cg, 65535);
 
+    // the host tables come first in scratch, in one piece, so that one copy
+    // uploads them
     msm::Carver cv;
     cv.take<Combo>((size_t)Cstd);
     cv.take<Combo>((size_t)std::max(1, Ch));
+    cv.take<Combo>(1);
     cv.take<uint64_t>(std::max<size_t>(1, fam.size()));
     cv.take<uint32_t>(std::max<size_t>(1, dtab.size()));
     cv.take<uint64_t>((size_t)k * MAXW);
+    const size_t table_bytes = cv.off;
     cv.take<unsigned long long>(4);
     cv.take<uint32_t>(4);
     cv.take<uint64_t>((size_t)Cg * n);
     cv.take<uint32_t>((size_t)Cg * nt * nb);
     cv.take<uint32_t>(hier_cand ? (size_t)(PROBE_HIER + PROBE_STD + 1) * PROBE_BINS : 1);
-    cv.take<Combo>(1);
+    cv.take<unsigned long long>(1);
     cv.take<uint32_t>((size_t)Cg * (nb + 1));
     cv.take<Ovf>((size_t)Cg * nb);
     cv.take<Ovf>((size_t)Cg * nb);
@@ -97,6 +103,7 @@ msm_status run_enumerate(msm_ctx* ctx, const uint64_t* S, int64_t n, int ell, in
     c2.base = static_cast<char*>(scr);
     Combo* d_combos_std = c2.take<Combo>((size_t)Cstd);
     Combo* d_combos_h = c2.take<Combo>((size_t)std::max(1, Ch));
+    Combo* d_full = c2.take<Combo>(1);
     uint64_t* d_fam = c2.take<uint64_t>(std::max<size_t>(1, fam.size()));
     uint32_t* d_dtab = c2.take<uint32_t>(std::max<size_t>(1, dtab.size()));
     uint64_t* d_bm = c2.take<uint64_t>((size_t)k * MAXW);
@@ -105,26 +112,30 @@ msm_status run_enumerate(msm_ctx* ctx, const uint64_t* S, int64_t n, int ell, in
     uint64_t* d_part = c2.take<uint64_t>((size_t)Cg * n);
     uint32_t* d_counts = c2.take<uint32_t>((size_t)Cg * nt * nb);
     uint32_t* d_probe = c2.take<uint32_t>(hier_cand ? (size_t)(PROBE_HIER + PROBE_STD + 1) * PROBE_BINS : 1);
-    Combo* d_full = c2.take<Combo>(1);
+    unsigned long long* d_work = c2.take<unsigned long long>(1);
     uint32_t* d_base = c2.take<uint32_t>((size_t)Cg * (nb + 1));
     Ovf* d_ovf = c2.take<Ovf>((size_t)Cg * nb);
     Ovf* d_ovf2 = c2.take<Ovf>((size_t)Cg * nb);
     uint64_t* d_tile0 = c2.take<uint64_t>((size_t)Cg * nb + 1);
 
-    MSM_HIP(ctx, hipMemcpyAsync(d_combos_std, combos.data(), sizeof(Combo) * Cstd, hipMemcpyHostToDevice, stream));
-    Combo full{};  // the whole string kept: groups of identical strings
-    for (int w = 0; w < MAXW; ++w) full.keep[w] = valid[w];
-    if (Ch > 0) {
-        MSM_HIP(ctx, hipMemcpyAsync(d_combos_h, parts.data(), sizeof(Combo) * Ch, hipMemcpyHostToDevice, stream));
-        MSM_HIP(ctx, hipMemcpyAsync(d_full, &full, sizeof(Combo), hipMemcpyHostToDevice, stream));
+    {
+        Combo full{};  // the whole string kept: groups of identical strings
+        for (int w = 0; w < MAXW; ++w) full.keep[w] = valid[w];
+        std::vector<char> blob(table_bytes, 0);
+        auto put = [&](const void* dev, const void* src, size_t bytes) {
+            if (bytes) std::memcpy(blob.data() + (static_cast<const char*>(dev) - c2.base), src, bytes);
+        };
+        put(d_combos_std, combos.data(), sizeof(Combo) * Cstd);
+        put(d_combos_h, parts.data(), sizeof(Combo) * Ch);
+        put(d_full, &full, sizeof(Combo));
+        put(d_fam, fam.data(), sizeof(uint64_t) * fam.size());
+        put(d_dtab, dtab.data(), sizeof(uint32_t) * dtab.size());
+        put(d_bm, bm.data(), sizeof(uint64_t) * bm.size());
+        MSM_HIP(ctx, hipMemcpyAsync(c2.base, blob.data(), table_bytes, hipMemcpyHostToDevice, stream));
+        // the copy is from pageable memory: it has read blob on return
     }
-    if (!fam.empty())
-        MSM_HIP(ctx, hipMemcpyAsync(d_fam, fam.data(), sizeof(uint64_t) * fam.size(), hipMemcpyHostToDevice, stream));
-    if (!dtab.empty())
-        MSM_HIP(ctx,
-                hipMemcpyAsync(d_dtab, dtab.data(), sizeof(uint32_t) * dtab.size(), hipMemcpyHostToDevice, stream));
-    MSM_HIP(ctx, hipMemcpyAsync(d_bm, bm.data(), sizeof(uint64_t) * bm.size(), hipMemcpyHostToDevice, stream));
     hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, stream, d_counter, 4);
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, stream, d_ovfc, 4);
 
     Params p{};
     p.S = S;
@@ -178,18 +189,11 @@ msm_status run_enumerate(msm_ctx* ctx, const uint64_t* S, int64_t n, int ell, in
                            stream, hist, nh * PROBE_BINS);
         const unsigned pg = (unsigned)((sample + 255) / 256);
         hipLaunchKernelGGL((k_probe_groups<W>), dim3(pg, nsh), dim3(256), 0, stream, S, sample, d_combos_h, hst,
-                           hist);
+                           hist, d_counter + 1);
         hipLaunchKernelGGL((k_probe_groups<W>), dim3(pg, nss), dim3(256), 0, stream, S, sample, d_combos_std, sst,
-                           hist + (size_t)nsh * PROBE_BINS);
+                           hist + (size_t)nsh * PROBE_BINS, d_counter + 2);
         hipLaunchKernelGGL((k_probe_groups<W>), dim3(pg, 1), dim3(256), 0, stream, S, sample, d_full, 0,
-                           hist + (size_t)(nsh + nss) * PROBE_BINS);
-        hipLaunchKernelGGL(k_bucket_sumsq, dim3((unsigned)(((int64_t)nsh * PROBE_BINS + 255) / 256)), dim3(256), 0,
-                           stream, (const uint32_t*)hist, 1, nsh * PROBE_BINS, d_counter + 1);
-        hipLaunchKernelGGL(k_bucket_sumsq, dim3((unsigned)(((int64_t)nss * PROBE_BINS + 255) / 256)), dim3(256), 0,
-                           stream, (const uint32_t*)(hist + (size_t)nsh * PROBE_BINS), 1, nss * PROBE_BINS,
-                           d_counter + 2);
-        hipLaunchKernelGGL(k_bucket_sumsq, dim3((PROBE_BINS + 255) / 256), dim3(256), 0, stream,
-                           (const uint32_t*)(hist + (size_t)(nsh + nss) * PROBE_BINS), 1, PROBE_BINS, d_counter + 3);
+                           hist + (size_t)(nsh + nss) * PROBE_BINS, d_counter + 3);
         MSM_HIP(ctx, hipGetLastError());
         MSM_HIP(ctx, hipMemcpyAsync(ctx->host_words, d_counter + 1, 3 * sizeof(uint64_t), hipMemcpyDeviceToHost,
                                     stream));
@@ -213,15 +217,13 @@ msm_status run_enumerate(msm_ctx* ctx, const uint64_t* S, int64_t n, int ell, in
     ctx->last_groupings = C;
     ctx->last_jblocks = hier ? jsel : 0;
 
-    std::vector<Ovf> hovf;
-    std::vector<uint64_t> htile;
     for (int rep = 0; rep < Q; ++rep) {
     p.rep = rep;
     p.S = S + (uint64_t)rep * p.rep_stride;
     for (int c0 = 0; c0 < C; c0 += Cg) {
         const int cc = std::min(Cg, C - c0);
         p.combos = d_combos + c0;
-        hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, stream, d_ovfc, 4);
+        hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, stream, d_ovfc, 3);  // [3] is the too-big flag
         p.units = cc * nt;
         const unsigned part_grid = (unsigned)((p.units + NUM_XCD - 1) / NUM_XCD * NUM_XCD);
         {
@@ -242,50 +244,33 @@ msm_status run_enumerate(msm_ctx* ctx, const uint64_t* S, int64_t n, int ell, in
             msm::KernelTimer kt(ctx, stream, "k_bucket");
             launch_bucket<W>(hm, false, dim3((nb + BK_GROUP - 1) / BK_GROUP, cc), stream, p);
         }
-        MSM_HIP(ctx, hipGetLastError());
-        MSM_HIP(ctx, hipMemcpyAsync(ctx->host_words, d_ovfc, sizeof(uint32_t), hipMemcpyDeviceToHost, stream));
-        MSM_HIP(ctx, hipStreamSynchronize(stream));
-        const uint32_t nlarge = *reinterpret_cast<uint32_t*>(ctx->host_words);
-        uint32_t novf = 0;
-        if (nlarge > 0) {
-            // buckets above the first pass's capacity: a second pass with
-            // more threads and LDS takes those up to its own capacity
-            p.list_cap = (uint32_t)cc * (uint32_t)nb;
-            {
-                msm::KernelTimer kt(ctx, stream, "k_bucket_large");
-                launch_bucket<W>(hm, true, dim3(nlarge), stream, p);
-            }
-            MSM_HIP(ctx, hipGetLastError());
-            MSM_HIP(ctx, hipMemcpyAsync(ctx->host_words, d_ovfc + 1, sizeof(uint32_t), hipMemcpyDeviceToHost,
-                                        stream));
-            MSM_HIP(ctx, hipStreamSynchronize(stream));
-            novf = *reinterpret_cast<uint32_t*>(ctx->host_words);
+        // Buckets above the first pass's capacity: a second pass with more
+        // threads and LDS takes those up to its own capacity, then tile pairs
+        // take the rest. Both read their work lists on the device with fixed
+        // grids, so the host does not wait for the first pass.
+        const uint32_t list_cap = (uint32_t)cc * (uint32_t)nb;
+        p.list_cap = list_cap;
+        const unsigned pgrid = (unsigned)std::min<int64_t>(list_cap, 2 * (int64_t)ctx->num_cu);
+        {
+            msm::KernelTimer kt(ctx, stream, "k_bucket_large");
+            launch_bucket<W>(hm, true, dim3(pgrid), stream, p);
         }
-        if (novf > 0) {
-            hovf.resize(novf);
-            MSM_HIP(ctx, hipMemcpy(hovf.data(), d_ovf2, sizeof(Ovf) * novf, hipMemcpyDeviceToHost));
-            htile.assign(novf + 1, 0);
-            for (uint32_t o = 0; o < novf; ++o) {
-                const uint64_t t = (hovf[o].m + BIG_TILE - 1) / BIG_TILE;
-                htile[o + 1] = htile[o] + t * (t + 1) / 2;
-            }
-            const uint64_t tiles = htile[novf];
-            if (tiles > 0x7FFFFFFFull)
-                return msm::fail(ctx, MSM_E_UNSUPPORTED,
-                                 "msm_enumerate_pairs: a group of %u equal strings is too large",
-                                 (unsigned)hovf[0].m);
-            MSM_HIP(ctx, hipMemcpyAsync(d_tile0, htile.data(), sizeof(uint64_t) * (novf + 1),
-                                        hipMemcpyHostToDevice, stream));
+        {
             msm::KernelTimer kt(ctx, stream, "k_big");
-            hipLaunchKernelGGL((k_big<W>), dim3((unsigned)tiles), dim3(BIG_TILE), 0, stream, p, d_ovf2,
-                               d_tile0, (int)novf);
-            MSM_HIP(ctx, hipGetLastError());
+            hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, stream, d_work, 1);
+            hipLaunchKernelGGL(k_ovf_prefix, dim3(1), dim3(1024), 0, stream, d_ovf2, d_ovfc + 1, list_cap, d_tile0);
+            hipLaunchKernelGGL((k_big<W, false>), dim3((unsigned)(2 * ctx->num_cu)), dim3(BIG_TILE), 0, stream, p,
+                               BatchArgs{}, d_ovf2, d_ovfc + 1, list_cap, d_tile0, d_work, d_ovfc + 3);
         }
+        MSM_HIP(ctx, hipGetLastError());
     }
     }
     MSM_HIP(ctx, hipMemcpyAsync(ctx->host_words, d_counter, sizeof(unsigned long long), hipMemcpyDeviceToHost,
                                 stream));
+    MSM_HIP(ctx, hipMemcpyAsync(ctx->host_words + 1, d_ovfc + 3, sizeof(uint32_t), hipMemcpyDeviceToHost, stream));
     MSM_HIP(ctx, hipStreamSynchronize(stream));
+    if (static_cast<uint32_t>(ctx->host_words[1]) != 0u)
+        return msm::fail(ctx, MSM_E_UNSUPPORTED, "msm_enumerate_pairs: a group of equal strings is too large");
     const int64_t m = (int64_t)ctx->host_words[0];
     *m_out = m;
     if (m > cap && !(pairs == nullptr && cap == 0))

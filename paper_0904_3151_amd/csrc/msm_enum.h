@@ -1140,29 +1140,6 @@ __device__ __forceinline__ void big_tile(const Params& p, const Ovf& e, int64_t 
     out.flush();
 }
 
-template <int W>
-__global__ __launch_bounds__(BIG_TILE) void k_big(Params p, const Ovf* __restrict__ ovf,
-                                                 const uint64_t* __restrict__ tile0, int novf)
-{
-    __shared__ uint64_t kR[BIG_TILE], kC[BIG_TILE];
-    __shared__ uint64_t sR[BIG_TILE * W], sC[BIG_TILE * W];
-    __shared__ uint64_t bmL[MAXK * W];
-    __shared__ uint2 obuf[BK_OUT];
-    __shared__ uint32_t ocnt;
-    __shared__ unsigned long long ogb;
-    if (threadIdx.x == 0) ocnt = 0;
-    msm::PairStager<BK_OUT> out{obuf, &ocnt, &ogb, p.pairs, p.cap, p.counter};
-    for (int x = threadIdx.x; x < p.k * W; x += BIG_TILE) bmL[x] = p.bm[(x / W) * MAXW + (x % W)];
-    const uint64_t tix = blockIdx.x;
-    int lo = 0, hi2 = novf;
-    while (hi2 - lo > 1) {
-        const int mid = (lo + hi2) >> 1;
-        if (tile0[mid] <= tix) lo = mid;
-        else hi2 = mid;
-    }
-    big_tile<W>(p, ovf[lo], (int64_t)(tix - tile0[lo]), BigShared{kR, kC, sR, sC, bmL}, out, 0u);
-}
-
 // Tile-pair counts of the overflow list, prefix-summed on the device:
 // tile0[o] = first tile pair of entry o, tile0[novf] = total. One workgroup.
 __global__ __launch_bounds__(1024) void k_ovf_prefix(const Ovf* __restrict__ ovf,
@@ -1202,15 +1179,20 @@ __global__ __launch_bounds__(1024) void k_ovf_prefix(const Ovf* __restrict__ ovf
     }
 }
 
-// Persistent form of k_big for batches: a fixed grid takes tile pairs from
-// a device work counter until the total of the overflow list is reached, so
-// the launch needs nothing from the host. Output goes to the instance of the
-// overflowing bucket (Ovf::pad) with indices local to it.
-template <int W>
-__global__ __launch_bounds__(BIG_TILE) void k_big_batch(Params p, BatchArgs ba, const Ovf* __restrict__ ovf,
-                                                       const uint32_t* __restrict__ ovf_count, uint32_t ovf_cap,
-                                                       const uint64_t* __restrict__ tile0,
-                                                       unsigned long long* __restrict__ work)
+// Buckets above every LDS pass's capacity: a fixed grid takes tile pairs
+// from a device work counter until the total of the overflow list
+// (k_ovf_prefix) is reached, so the launch needs nothing from the host. In a
+// batch (BATCH) output goes to the instance of the overflowing bucket
+// (Ovf::pad) with indices local to it, else to p.pairs. With `too_big` set,
+// a list of more than BIG_TILE_LIMIT tile pairs (a group of some 16M equal
+// strings) is not started and the flag is raised instead.
+constexpr uint64_t BIG_TILE_LIMIT = 0x7FFFFFFFull;
+
+template <int W, bool BATCH>
+__global__ __launch_bounds__(BIG_TILE) void k_big(Params p, BatchArgs ba, const Ovf* __restrict__ ovf,
+                                                 const uint32_t* __restrict__ ovf_count, uint32_t ovf_cap,
+                                                 const uint64_t* __restrict__ tile0,
+                                                 unsigned long long* __restrict__ work, uint32_t* too_big)
 {
     __shared__ uint64_t kR[BIG_TILE], kC[BIG_TILE];
     __shared__ uint64_t sR[BIG_TILE * W], sC[BIG_TILE * W];
@@ -1220,10 +1202,14 @@ __global__ __launch_bounds__(BIG_TILE) void k_big_batch(Params p, BatchArgs ba, 
     __shared__ unsigned long long ogb;
     __shared__ unsigned long long task;
     if (threadIdx.x == 0) ocnt = 0;
-    msm::PairStager<BK_OUT> out{obuf, &ocnt, &ogb, nullptr, 0ull, nullptr};
+    msm::PairStager<BK_OUT> out{obuf, &ocnt, &ogb, p.pairs, p.cap, p.counter};
     for (int x = threadIdx.x; x < p.k * W; x += BIG_TILE) bmL[x] = p.bm[(x / W) * MAXW + (x % W)];
     const int novf = (int)min(*ovf_count, ovf_cap);
     const uint64_t total = tile0[novf];
+    if (too_big && total > BIG_TILE_LIMIT) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) *too_big = 1u;
+        return;
+    }
     while (true) {
         __syncthreads();  // everyone has read the previous task
         if (threadIdx.x == 0) task = atomicAdd(work, 1ull);
@@ -1237,11 +1223,16 @@ __global__ __launch_bounds__(BIG_TILE) void k_big_batch(Params p, BatchArgs ba, 
             else hi2 = mid;
         }
         const Ovf e = ovf[lo];
-        const BInst& in = ba.inst[e.pad];
-        out.out = in.pairs;
-        out.cap = (unsigned long long)in.cap;
-        out.counter = ba.m_dev + e.pad;
-        big_tile<W>(p, e, (int64_t)(tix - tile0[lo]), BigShared{kR, kC, sR, sC, bmL}, out, (uint32_t)in.off);
+        uint32_t o_off = 0;
+        if (BATCH) {
+            // output to the bucket's instance
+            const BInst& in = ba.inst[e.pad];
+            out.out = in.pairs;
+            out.cap = (unsigned long long)in.cap;
+            out.counter = ba.m_dev + e.pad;
+            o_off = (uint32_t)in.off;
+        }
+        big_tile<W>(p, e, (int64_t)(tix - tile0[lo]), BigShared{kR, kC, sR, sC, bmL}, out, o_off);
     }
 }
 
@@ -1252,32 +1243,32 @@ constexpr int PROBE_BINS = 1 << PROBE_LOG;
 constexpr int PROBE_HIER = 64;  // hierarchical groupings probed, at most
 constexpr int PROBE_STD = 4;    // per-combination groupings probed
 
+// The sum of squared bin sizes is accumulated on the way: a bin going from
+// c to c + 1 members adds 2c + 1 to it. 256 threads per workgroup.
 template <int W>
-__global__ void k_probe_groups(const uint64_t* __restrict__ S, int64_t sample, const Combo* __restrict__ base,
-                               int stride, uint32_t* __restrict__ hist)
+__global__ __launch_bounds__(256) void k_probe_groups(const uint64_t* __restrict__ S, int64_t sample,
+                                                      const Combo* __restrict__ base, int stride,
+                                                      uint32_t* __restrict__ hist, unsigned long long* sumsq)
 {
+    __shared__ unsigned long long wsum[4];
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= sample) return;
-    const Combo* cb = base + (size_t)blockIdx.y * stride;
-    uint64_t keep[W], s[W];
-    load_keep<W>(cb, keep);
-    load_string<W>(S, (uint64_t)i, s);
-    atomicAdd(&hist[(size_t)blockIdx.y * PROBE_BINS + (masked_mix<W>(s, keep) >> (32 - PROBE_LOG))], 1u);
-}
-
-// Sum over buckets of the squared bucket size, from the tile counts of one
-// grouping (counts[t][b], nt tiles, nb buckets).
-__global__ void k_bucket_sumsq(const uint32_t* __restrict__ counts, int nt, int nb, unsigned long long* out)
-{
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
     unsigned long long v = 0;
-    if (b < nb) {
-        uint32_t c = 0;
-        for (int t = 0; t < nt; ++t) c += counts[(size_t)t * nb + b];
-        v = (unsigned long long)c * c;
+    if (i < sample) {
+        const Combo* cb = base + (size_t)blockIdx.y * stride;
+        uint64_t keep[W], s[W];
+        load_keep<W>(cb, keep);
+        load_string<W>(S, (uint64_t)i, s);
+        const uint32_t old =
+            atomicAdd(&hist[(size_t)blockIdx.y * PROBE_BINS + (masked_mix<W>(s, keep) >> (32 - PROBE_LOG))], 1u);
+        v = 2ull * old + 1ull;
     }
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    if ((threadIdx.x & 63) == 0 && v) atomicAdd(out, v);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned long long t = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+        if (t) atomicAdd(sumsq, t);
+    }
 }
 
 __global__ void k_zero_u64(unsigned long long* a, int n)
