@@ -233,6 +233,8 @@ msm_status run_enumerate(msm_ctx* ctx, const uint64_t* S, int64_t n, int ell, in
         }
         {
             msm::KernelTimer kt(ctx, stream, "k_part_scan");
+            hipLaunchKernelGGL(k_part_colscan, dim3((nb + PART_THREADS - 1) / PART_THREADS, cc), dim3(PART_THREADS), 0,
+                               stream, p);
             hipLaunchKernelGGL(k_part_scan, dim3(cc), dim3(SCAN_THREADS), (nb + 32) * sizeof(uint32_t), stream, p);
         }
         {

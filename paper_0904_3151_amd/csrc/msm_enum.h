@@ -11,7 +11,7 @@
 //
 //   1. partition  one MSD radix pass over HBM on the top r1 bits of the mix:
 //                 LDS histograms per tile (k_part_count), a column scan of
-//                 the (tile, bucket) counts (k_part_scan), and a scatter of
+//                 the (tile, bucket) counts (k_part_colscan, k_part_scan), and a scatter of
 //                 (mix << 32 | index) into bucket order (k_part_scatter).
 //   2. bucket     a workgroup takes a few buckets (about 512 points each):
 //                 the next 11 bits of the mix are counted in an LDS
@@ -232,32 +232,42 @@ __global__ __launch_bounds__(PART_THREADS) void k_part_count(Params p)
 }
 
 // Per combination: counts[t][b] -> offset of tile t inside bucket b, and
-// base[b] = start of bucket b.
+// base[b] = start of bucket b, in two launches: a column scan over the
+// tiles with one thread per bucket (grid: buckets / PART_THREADS x
+// combinations), which leaves bucket totals in base, then one workgroup
+// per combination turns the totals into starts.
+__global__ __launch_bounds__(PART_THREADS) void k_part_colscan(Params p)
+{
+    const int cl = blockIdx.y;
+    const int b = blockIdx.x * PART_THREADS + threadIdx.x;
+    if (b >= p.nb) return;
+    uint32_t* cnt = p.counts + (size_t)cl * p.nt * p.nb;
+    uint32_t run = 0;
+    int t = 0;
+    for (; t + 8 <= p.nt; t += 8) {
+        uint32_t v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = cnt[(size_t)(t + q) * p.nb + b];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            cnt[(size_t)(t + q) * p.nb + b] = run;
+            run += v[q];
+        }
+    }
+    for (; t < p.nt; ++t) {
+        const uint32_t v = cnt[(size_t)t * p.nb + b];
+        cnt[(size_t)t * p.nb + b] = run;
+        run += v;
+    }
+    p.base[(size_t)cl * (p.nb + 1) + b] = run;
+}
+
 __global__ __launch_bounds__(SCAN_THREADS) void k_part_scan(Params p)
 {
     extern __shared__ uint32_t tot[];  // nb totals, then one word per wave
     const int cl = blockIdx.x;
-    uint32_t* cnt = p.counts + (size_t)cl * p.nt * p.nb;
-    for (int b = threadIdx.x; b < p.nb; b += SCAN_THREADS) {
-        uint32_t run = 0;
-        int t = 0;
-        for (; t + 8 <= p.nt; t += 8) {
-            uint32_t v[8];
-#pragma unroll
-            for (int q = 0; q < 8; ++q) v[q] = cnt[(size_t)(t + q) * p.nb + b];
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                cnt[(size_t)(t + q) * p.nb + b] = run;
-                run += v[q];
-            }
-        }
-        for (; t < p.nt; ++t) {
-            const uint32_t v = cnt[(size_t)t * p.nb + b];
-            cnt[(size_t)t * p.nb + b] = run;
-            run += v;
-        }
-        tot[b] = run;
-    }
+    uint32_t* base = p.base + (size_t)cl * (p.nb + 1);
+    for (int b = threadIdx.x; b < p.nb; b += SCAN_THREADS) tot[b] = base[b];
     __syncthreads();
     uint32_t* wsum = tot + p.nb;
     const int per = (p.nb + SCAN_THREADS - 1) / SCAN_THREADS;
@@ -272,7 +282,6 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_part_scan(Params p)
     uint32_t pre = 0;
     for (int w = 0; w < wave; ++w) pre += wsum[w];
     uint32_t run = pre + incl - s;
-    uint32_t* base = p.base + (size_t)cl * (p.nb + 1);
     for (int b = b0; b < b1; ++b) {
         const uint32_t v = tot[b];
         base[b] = run;
