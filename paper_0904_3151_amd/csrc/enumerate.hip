@@ -188,12 +188,8 @@ msm_status run_enumerate(msm_ctx* ctx, const uint64_t* S, int64_t n, int ell, in
         hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)(((int64_t)nh * PROBE_BINS + 255) / 256)), dim3(256), 0,
                            stream, hist, nh * PROBE_BINS);
         const unsigned pg = (unsigned)((sample + 255) / 256);
-        hipLaunchKernelGGL((k_probe_groups<W>), dim3(pg, nsh), dim3(256), 0, stream, S, sample, d_combos_h, hst,
-                           hist, d_counter + 1);
-        hipLaunchKernelGGL((k_probe_groups<W>), dim3(pg, nss), dim3(256), 0, stream, S, sample, d_combos_std, sst,
-                           hist + (size_t)nsh * PROBE_BINS, d_counter + 2);
-        hipLaunchKernelGGL((k_probe_groups<W>), dim3(pg, 1), dim3(256), 0, stream, S, sample, d_full, 0,
-                           hist + (size_t)(nsh + nss) * PROBE_BINS, d_counter + 3);
+        hipLaunchKernelGGL((k_probe_groups<W>), dim3(pg, nh), dim3(256), 0, stream, S, sample, d_combos_h, nsh, hst,
+                           d_combos_std, nss, sst, d_full, hist, d_counter + 1);
         MSM_HIP(ctx, hipGetLastError());
         MSM_HIP(ctx, hipMemcpyAsync(ctx->host_words, d_counter + 1, 3 * sizeof(uint64_t), hipMemcpyDeviceToHost,
                                     stream));

@@ -1252,23 +1252,30 @@ constexpr int PROBE_BINS = 1 << PROBE_LOG;
 constexpr int PROBE_HIER = 64;  // hierarchical groupings probed, at most
 constexpr int PROBE_STD = 4;    // per-combination groupings probed
 
-// The sum of squared bin sizes is accumulated on the way: a bin going from
-// c to c + 1 members adds 2c + 1 to it. 256 threads per workgroup.
+// Rows blockIdx.y < nh of the grid probe hierarchical groupings hc + y * hs,
+// the next ns rows per-combination groupings sc + (y - nh) * ss, the last
+// row the whole string (full). The sum of squared bin sizes of each kind is
+// accumulated on the way into sumsq[kind]: a bin going from c to c + 1
+// members adds 2c + 1 to it. 256 threads per workgroup.
 template <int W>
 __global__ __launch_bounds__(256) void k_probe_groups(const uint64_t* __restrict__ S, int64_t sample,
-                                                      const Combo* __restrict__ base, int stride,
-                                                      uint32_t* __restrict__ hist, unsigned long long* sumsq)
+                                                      const Combo* __restrict__ hc, int nh, int hs,
+                                                      const Combo* __restrict__ sc, int ns, int ss,
+                                                      const Combo* __restrict__ full, uint32_t* __restrict__ hist,
+                                                      unsigned long long* sumsq)
 {
     __shared__ unsigned long long wsum[4];
+    const int y = (int)blockIdx.y;
+    const int kind = y < nh ? 0 : (y < nh + ns ? 1 : 2);
+    const Combo* cb = kind == 0 ? hc + (size_t)y * hs : (kind == 1 ? sc + (size_t)(y - nh) * ss : full);
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     unsigned long long v = 0;
     if (i < sample) {
-        const Combo* cb = base + (size_t)blockIdx.y * stride;
         uint64_t keep[W], s[W];
         load_keep<W>(cb, keep);
         load_string<W>(S, (uint64_t)i, s);
         const uint32_t old =
-            atomicAdd(&hist[(size_t)blockIdx.y * PROBE_BINS + (masked_mix<W>(s, keep) >> (32 - PROBE_LOG))], 1u);
+            atomicAdd(&hist[(size_t)y * PROBE_BINS + (masked_mix<W>(s, keep) >> (32 - PROBE_LOG))], 1u);
         v = 2ull * old + 1ull;
     }
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -1276,7 +1283,7 @@ __global__ __launch_bounds__(256) void k_probe_groups(const uint64_t* __restrict
     __syncthreads();
     if (threadIdx.x == 0) {
         const unsigned long long t = wsum[0] + wsum[1] + wsum[2] + wsum[3];
-        if (t) atomicAdd(sumsq, t);
+        if (t) atomicAdd(sumsq + kind, t);
     }
 }
 
