@@ -130,8 +130,10 @@ msm_status msm_project_lowp(msm_ctx* ctx, const float* X, int64_t n, int32_t d, 
  * The result set does not depend on k; k only changes the work.
  * Limits: n < 2^32, 1 <= ell <= 256, 0 <= h < k <= min(ell, 64),
  * C(k, h) <= 65536.
- * Errors: MSM_E_INVALID (sizes, NULL pointers), MSM_E_UNSUPPORTED (k > 64
- * or too many combinations), MSM_E_CAPACITY when the count exceeds cap:
+ * Errors: MSM_E_INVALID (sizes, NULL pointers), MSM_E_UNSUPPORTED (k > 64,
+ * too many combinations, or a group of more than about 16.7M strings that
+ * agree under some grouping: its pairs are not tested), MSM_E_CAPACITY when
+ * the count exceeds cap:
  * *m_out then holds the required count and the contents of pairs are
  * undefined. pairs == NULL with cap == 0 is a count-only call. Synchronises
  * `stream` before returning. */

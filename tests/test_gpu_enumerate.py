@@ -181,3 +181,19 @@ def test_hierarchical_layouts(msm, ctx, ell, k, h, groupings):
     assert check(msm, ctx, S, ell, k, h) > 0
     g, j = msm.msm_enumerate_last_plan(ctx)
     assert g == groupings and j > 0
+
+
+def test_enumerate_rejects_a_group_beyond_the_tile_limit(msm, ctx):
+    """17M equal strings form one group of 1.4e14 pairs in every grouping:
+    the call returns MSM_E_UNSUPPORTED without testing them, and a normal
+    call on the same context works afterwards."""
+    n = 17_000_000
+    S = torch.zeros((n, 1), dtype=torch.int64, device="cuda")
+    announce("enumerate too-big group", n)
+    with pytest.raises(msm.MSMError) as e:
+        msm.msm_enumerate_pairs(ctx, S, 64, 5, 3, cap=0)
+    assert e.value.status == msm.MSM_E_UNSUPPORTED
+    del S
+    torch.cuda.empty_cache()
+    Ssmall = I.random_strings(3000, 64, seed=5, n_seeds=300, flips=4)
+    check(msm, ctx, Ssmall, 64, 5, 3)
