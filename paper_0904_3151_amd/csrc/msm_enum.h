@@ -892,11 +892,15 @@ __global__ __launch_bounds__(TH, (TH == BK_THREADS && W <= 2 && DIGIT <= 10) ? 4
                     uint64_t bits = 0;
                     if constexpr (HIER) {
                         // every block in which the member differs from the first
-                        for (int blk = 0; blk < p.k; ++blk) {
-                            uint64_t any = 0;
+                        if constexpr (HM != 1) {
+                            bits = diff_blocks_of<W, HM>(x, p);
+                        } else {
+                            for (int blk = 0; blk < p.k; ++blk) {
+                                uint64_t any = 0;
 #pragma unroll
-                            for (int w = 0; w < W; ++w) any |= x[w] & bmL[blk * W + w];
-                            bits |= any ? (1ull << blk) : 0ull;
+                                for (int w = 0; w < W; ++w) any |= x[w] & bmL[blk * W + w];
+                                bits |= any ? (1ull << blk) : 0ull;
+                            }
                         }
                         if (bits) atomicOr(&runBlk[rrun[b]], (unsigned long long)bits);
                     } else {
