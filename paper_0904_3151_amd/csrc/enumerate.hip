@@ -7,9 +7,10 @@
 
 namespace {
 
-// The bucket kernel instantiated for the grouping mode hm (0: one grouping
-// per combination; hierarchical: 8, 16 or 32 for blocks of that many
-// characters, 1 for other layouts; GT when the family bitmaps over 2^k
+// The bucket kernel instantiated for the grouping mode hm (one grouping per
+// combination: 0, or -8, -16, -32 for blocks of that many characters;
+// hierarchical: 8, 16 or 32 for blocks of that many characters, 1 for other
+// layouts; GT when the family bitmaps over 2^k
 // difference sets are too large for LDS): the first pass, or (large) the
 // second pass over buckets above the first pass's capacity.
 template <int W, int HM, bool GT>
@@ -38,6 +39,9 @@ template <int W>
 void launch_bucket(int hm, bool large, dim3 grid, hipStream_t stream, const Params& p)
 {
     if (hm == 0) launch_bucket_mode<W, 0, false>(large, grid, stream, p);
+    else if (hm == -8) launch_bucket_mode<W, -8, false>(large, grid, stream, p);
+    else if (hm == -16) launch_bucket_mode<W, -16, false>(large, grid, stream, p);
+    else if (hm == -32) launch_bucket_mode<W, -32, false>(large, grid, stream, p);
     else if (p.k <= DT_LDS_K) launch_bucket_hier<W, false>(hm, large, grid, stream, p);
     else launch_bucket_hier<W, true>(hm, large, grid, stream, p);
 }
@@ -209,7 +213,7 @@ msm_status run_enumerate(msm_ctx* ctx, const uint64_t* S, int64_t n, int ell, in
     p.hier = hier ? 1 : 0;
     p.fam = hier ? d_fam : nullptr;
     p.dtab = hier ? d_dtab : nullptr;
-    const int hm = hier ? (p.dL ? p.dL : 1) : 0;
+    const int hm = hier ? (p.dL ? p.dL : 1) : -p.dL;
     ctx->last_groupings = C;
     ctx->last_jblocks = hier ? jsel : 0;
 

@@ -83,7 +83,7 @@ struct Combo {                    // one set B of masked blocks (or, grouped
     uint64_t hi;                  // blocks of B above the smallest block not in B
     int32_t nhi;                  // number of blocks in hi
     int32_t nfam;                 // hierarchical: difference sets of the family
-    uint64_t amask;               // hierarchical: the partition's blocks A
+    uint64_t amask;               // the masked blocks B (per combination) or the partition's blocks A
     uint32_t famoff;              // hierarchical: first family entry in Params::fam
     uint32_t dtoff;               // hierarchical: first word of its bitmap in Params::dtab
     uint64_t himask[MAXHI][MAXW]; // character masks of the first MAXHI blocks of hi
@@ -456,14 +456,18 @@ __device__ __forceinline__ bool pair_ok(const uint64_t* a, const uint64_t* b, co
 // The same test, branch-free, with the masks of the first MAXHI blocks of
 // `hi` held in registers (hm). Combinations with more blocks in `hi` finish
 // with a loop over the block masks in LDS. HM is 0 for one grouping per
-// combination, else the hierarchical block layout (see diff_blocks_of); GT
+// combination; -8, -16 or -32 for the same with blocks of that many
+// characters, where the test is on the difference set D itself (hi <= D <=
+// B, with B the combination's masked blocks bmask); positive for the
+// hierarchical partitions with that block layout (see diff_blocks_of). GT
 // reads the family bitmap from global memory (k > DT_LDS_K), else from LDS.
 // A hierarchical partition keeps every block outside its family's union, so
 // the bitmap alone also rejects pairs that differ in a kept block.
 template <int W, int HM, bool GT>
 __device__ __forceinline__ bool pair_ok_fast(const uint64_t* a, const uint64_t* b, const Params& p,
                                              const uint64_t (&keep)[W], const uint64_t (&hm)[MAXHI][W], int nhi,
-                                             uint64_t hi_rest, const uint32_t* dtabL, const uint32_t* dtabG,
+                                             uint64_t hi_rest, uint64_t bmask, uint64_t hi,
+                                             const uint32_t* dtabL, const uint32_t* dtabG,
                                              const uint64_t* __restrict__ bmL)
 {
     // the strings in LDS are already cut to ell characters
@@ -477,7 +481,12 @@ __device__ __forceinline__ bool pair_ok_fast(const uint64_t* a, const uint64_t* 
         if constexpr (HM == 0) outside |= x[w] & keep[w];
     }
     bool ok = (ham <= p.h) & (outside == 0);
-    if constexpr (HM != 0) {
+    if constexpr (HM < 0) {
+        const uint32_t D = diff_blocks_of<W, -HM>(x, p);
+        const uint32_t Bm = (uint32_t)bmask, H = (uint32_t)hi;
+        return ok & ((D & ~Bm) == 0u) & ((D & H) == H);
+    }
+    if constexpr (HM > 0) {
         // the pair's difference set must be in the partition's family
         uint32_t D = 0;
         if constexpr (HM != 1) D = diff_blocks_of<W, HM>(x, p);
@@ -639,7 +648,7 @@ template <int W, int DIGIT, bool BATCH, int TH, bool LIST, int MAXB, int HM, boo
 __global__ __launch_bounds__(TH, (TH == BK_THREADS && W <= 2 && DIGIT <= 10) ? 4 : 1) void k_bucket(Params p,
                                                                                                    BatchArgs ba)
 {
-    constexpr bool HIER = HM != 0;
+    constexpr bool HIER = HM > 0;
     constexpr int BINS = 1 << DIGIT;
     constexpr int CAP = TH * MAXB;
     // hist holds the digit counts, then (for bins that form runs) the run's
@@ -667,6 +676,7 @@ __global__ __launch_bounds__(TH, (TH == BK_THREADS && W <= 2 && DIGIT <= 10) ? 4
     int cl = -1;
     uint64_t keep[W];
     uint64_t hi = 0;
+    uint64_t bmask = 0;
     int nhi = 0;
     uint64_t hm[MAXHI][W];
     int hb[MAXHI];
@@ -679,6 +689,7 @@ __global__ __launch_bounds__(TH, (TH == BK_THREADS && W <= 2 && DIGIT <= 10) ? 4
         const Combo* cb = p.combos + c;
         load_keep<W>(cb, keep);
         hi = cb->hi;
+        bmask = cb->amask;
         nhi = cb->nhi;
         nfam = cb->nfam;
         fam = p.fam ? p.fam + cb->famoff : nullptr;
@@ -903,6 +914,9 @@ __global__ __launch_bounds__(TH, (TH == BK_THREADS && W <= 2 && DIGIT <= 10) ? 4
                             }
                         }
                         if (bits) atomicOr(&runBlk[rrun[b]], (unsigned long long)bits);
+                    } else if constexpr (HM < 0) {
+                        bits = diff_blocks_of<W, -HM>(x, p) & hi;
+                        if (bits) atomicOr(&runBlk[rrun[b]], (unsigned long long)bits);
                     } else {
 #pragma unroll
                         for (int s2 = 0; s2 < MAXHI; ++s2) {
@@ -1031,7 +1045,8 @@ __global__ __launch_bounds__(TH, (TH == BK_THREADS && W <= 2 && DIGIT <= 10) ? 4
                 }
                 const bool live = t + q < P;
                 const bool ok =
-                    live & pair_ok_fast<W, HM, GT>(sa, sb, p, keep, hm, nhi, hi_rest, dtabL, dtabG, bmL);
+                    live & pair_ok_fast<W, HM, GT>(sa, sb, p, keep, hm, nhi, hi_rest, bmask, hi, dtabL, dtabG,
+                                                  bmL);
                 okbits |= (uint32_t)ok << q;
                 if (more) {
 #pragma unroll
@@ -1352,6 +1367,7 @@ inline void build_tables(int ell, int k, int h, std::vector<uint64_t>& bm, uint6
             for (int b = lowest_kept + 1; b < k; ++b)
                 if ((Bm >> b) & 1ull) hi |= 1ull << b;
             cb.hi = hi;
+            cb.amask = Bm;
             cb.nhi = __builtin_popcountll(hi);
             {
                 int slot = 0;

@@ -2,6 +2,7 @@
 the GPU pair set must equal {(i, j): i < j, HamDist(s_i, s_j) <= h} exactly
 (computed by the oracle's exhaustive search), with every pair once."""
 import ctypes
+import math
 
 import numpy as np
 import pytest
@@ -197,3 +198,29 @@ def test_enumerate_rejects_a_group_beyond_the_tile_limit(msm, ctx):
     torch.cuda.empty_cache()
     Ssmall = I.random_strings(3000, 64, seed=5, n_seeds=300, flips=4)
     check(msm, ctx, Ssmall, 64, 5, 3)
+
+
+def two_valued_blocks(n, ell, k, flips, seed):
+    """Strings whose every block is one of two fixed values, then up to
+    `flips` random flips: j kept blocks split the points into few groups,
+    so one grouping per combination is the cheaper plan."""
+    rng = np.random.default_rng(seed)
+    L = ell // k
+    vals = rng.integers(0, 2, size=(k, 2, L), dtype=np.uint8)
+    choice = rng.integers(0, 2, size=(n, k))
+    bits = np.concatenate([vals[b, choice[:, b]] for b in range(k)], axis=1)
+    for r in range(n):
+        f = rng.integers(0, flips + 1)
+        if f:
+            bits[r, rng.choice(ell, size=f, replace=False)] ^= 1
+    return I.pack_bits(bits, (ell + 63) // 64)
+
+
+@pytest.mark.parametrize("ell,k,h", [(128, 16, 3), (128, 8, 2), (128, 4, 1), (64, 8, 2)])
+def test_per_combination_field_layouts(msm, ctx, ell, k, h):
+    """One grouping per combination on 8-, 16- and 32-character blocks, where
+    the pair test works on the difference set of blocks."""
+    S = two_valued_blocks(3000, ell, k, h + 1, seed=ell + 7 * k + h)
+    assert check(msm, ctx, S, ell, k, h) > 0
+    g, j = msm.msm_enumerate_last_plan(ctx)
+    assert j == 0 and g == math.comb(k, h)
