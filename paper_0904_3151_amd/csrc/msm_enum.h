@@ -54,7 +54,7 @@ constexpr int BK_THREADS = 256;
 constexpr int BK_WAVES = BK_THREADS / 64;
 constexpr int BK_MAXB = 4;                        // 64-element batches per wave
 constexpr int BK_CAP = BK_WAVES * 64 * BK_MAXB;   // largest bucket sorted in LDS
-constexpr int BK_PAIR_CHUNK = 8;                  // consecutive pairs per lane
+constexpr int BK_PAIR_MAX = 32;                   // consecutive pairs per lane and round, at most
 constexpr int BK_GROUP = 2;                       // buckets per workgroup
 constexpr int BK_OUT = 512;                       // staged output pairs per workgroup
 constexpr int BK_DIGIT = 10;                      // mix bits counted inside a bucket
@@ -971,15 +971,33 @@ __global__ __launch_bounds__(TH, (TH == BK_THREADS && W <= 2 && DIGIT <= 10) ? 4
         const uint32_t P = (uint32_t)claimPair;
         if (P == 0) continue;
 
-        // Flat loop over all claimed pairs (a < b), row-major per run; each
-        // lane tests BK_PAIR_CHUNK consecutive pairs, keeps the results in a
-        // bit mask and appends the passing ones once per chunk.
-        // pairs per lane: as few as spread P over the workgroup, at most
-        // BK_PAIR_CHUNK (uniform, so the unrolled loops below stop early)
-        const int cpl = (int)min((uint32_t)BK_PAIR_CHUNK, (P + TH - 1) / TH);
+        // Flat loop over all claimed pairs (a < b), row-major per run. Each
+        // lane walks cpl consecutive pairs: as few as spread P over the
+        // workgroup, at most BK_PAIR_MAX, so that most buckets take a single
+        // round with every lane busy. It keeps the results in a bit mask and
+        // appends the passing pairs once per round, walking its pairs a
+        // second time for their point indices.
+        const int cpl = (int)min((uint32_t)BK_PAIR_MAX, (P + TH - 1) / TH);
+        // next pair in row-major order over the live runs
+        auto advance = [&](int& r, int& a, int& bb, int& L, int& s0) {
+            ++bb;
+            if (bb == L) {
+                ++a;
+                bb = a + 1;
+                if (a >= L - 1) {
+                    ++r;
+                    a = 0;
+                    bb = 1;
+                    const int rr = min(r, (int)nlive - 1);
+                    L = liveL[rr];
+                    s0 = liveS[rr];
+                }
+            }
+        };
         for (uint32_t t0 = 0; t0 < P; t0 += TH * (uint32_t)cpl) {
             const uint32_t t = t0 + threadIdx.x * (uint32_t)cpl;
             int r = 0, a = 0, bb = 1, L = 2, s0 = 0;
+            int nq = 0;  // pairs of this lane
             if (t < P) {
                 int lo = 0, hi2 = (int)nlive;
                 while (hi2 - lo > 1) {
@@ -1000,55 +1018,35 @@ __global__ __launch_bounds__(TH, (TH == BK_THREADS && W <= 2 && DIGIT <= 10) ? 4
                 if (aa > 0 && (uint32_t)(aa * (2 * L - aa - 1) / 2) > u) --aa;
                 a = aa;
                 bb = a + 1 + (int)(u - (uint32_t)(a * (2 * L - a - 1) / 2));
+                nq = (int)min((uint32_t)cpl, P - t);
             }
-            // positions of the chunk's candidates first, then the tests
-            int pa[BK_PAIR_CHUNK], pb[BK_PAIR_CHUNK];
-#pragma unroll
-            for (int q = 0; q < BK_PAIR_CHUNK; ++q) {
-                if (q >= cpl) break;
-                pa[q] = min(s0 + a, CAP - 1);
-                pb[q] = min(s0 + bb, CAP - 1);
-                ++bb;
-                const bool wrapRow = bb == L;
-                a += wrapRow;
-                bb = wrapRow ? a + 1 : bb;
-                if (wrapRow && a >= L - 1) {
-                    ++r;
-                    a = 0;
-                    bb = 1;
-                    const int rr = min(r, (int)nlive - 1);
-                    L = liveL[rr];
-                    s0 = liveS[rr];
-                }
-            }
+            const int r_0 = r, a_0 = a, b_0 = bb, L_0 = L, s_0 = s0;
             uint32_t okbits = 0;
-            // the next candidate's strings are requested before the current
-            // one is tested; point indices are read from LDS only for the
-            // pairs that pass
-            uint64_t sa[W], sb[W];
-#pragma unroll
-            for (int w = 0; w < W; ++w) {
-                sa[w] = sl[pa[0] * W + w];
-                sb[w] = sl[pb[0] * W + w];
-            }
-#pragma unroll
-            for (int q = 0; q < BK_PAIR_CHUNK; ++q) {
-                if (q >= cpl) break;
-                uint64_t na[W], nb[W];
-                const bool more = q + 1 < BK_PAIR_CHUNK && q + 1 < cpl;
-                if (more) {
+            {
+                // the next candidate's strings are requested before the
+                // current one is tested (positions are clamped to the
+                // arrays: past a lane's last pair they are not used)
+                uint64_t sa[W], sb[W];
+                {
+                    const int pa = min(s0 + a, CAP - 1), pb = min(s0 + bb, CAP - 1);
 #pragma unroll
                     for (int w = 0; w < W; ++w) {
-                        na[w] = sl[pa[q + 1 < BK_PAIR_CHUNK ? q + 1 : q] * W + w];
-                        nb[w] = sl[pb[q + 1 < BK_PAIR_CHUNK ? q + 1 : q] * W + w];
+                        sa[w] = sl[pa * W + w];
+                        sb[w] = sl[pb * W + w];
                     }
                 }
-                const bool live = t + q < P;
-                const bool ok =
-                    live & pair_ok_fast<W, HM, GT>(sa, sb, p, keep, hm, nhi, hi_rest, bmask, hi, dtabL, dtabG,
-                                                  bmL);
-                okbits |= (uint32_t)ok << q;
-                if (more) {
+                for (int q = 0; q < nq; ++q) {
+                    advance(r, a, bb, L, s0);
+                    const int pa = min(s0 + a, CAP - 1), pb = min(s0 + bb, CAP - 1);
+                    uint64_t na[W], nb[W];
+#pragma unroll
+                    for (int w = 0; w < W; ++w) {
+                        na[w] = sl[pa * W + w];
+                        nb[w] = sl[pb * W + w];
+                    }
+                    const bool ok =
+                        pair_ok_fast<W, HM, GT>(sa, sb, p, keep, hm, nhi, hi_rest, bmask, hi, dtabL, dtabG, bmL);
+                    okbits |= (uint32_t)ok << q;
 #pragma unroll
                     for (int w = 0; w < W; ++w) {
                         sa[w] = na[w];
@@ -1056,15 +1054,17 @@ __global__ __launch_bounds__(TH, (TH == BK_THREADS && W <= 2 && DIGIT <= 10) ? 4
                     }
                 }
             }
+            // point indices are read from LDS only for the pairs that pass
             if (p.rep > 0 && okbits) {
-#pragma unroll
-                for (int q = 0; q < BK_PAIR_CHUNK; ++q) {
-                    if (q >= cpl) break;
-                    if (((okbits >> q) & 1u) && !far_in_earlier<W>(p, idxB[pa[q]], idxB[pb[q]]))
+                int r2 = r_0, a2 = a_0, b2 = b_0, L2 = L_0, s2 = s_0;
+                for (int q = 0; q < nq; ++q) {
+                    if (((okbits >> q) & 1u) &&
+                        !far_in_earlier<W>(p, idxB[min(s2 + a2, CAP - 1)], idxB[min(s2 + b2, CAP - 1)]))
                         okbits &= ~(1u << q);
+                    advance(r2, a2, b2, L2, s2);
                 }
             }
-            // one append per lane per chunk: wave prefix of the counts, one
+            // one append per lane per round: wave prefix of the counts, one
             // LDS atomic per wave
             const uint32_t nmine = (uint32_t)__popc(okbits);
             const uint32_t incl = msm::wave_incl_scan(nmine);
@@ -1084,20 +1084,22 @@ __global__ __launch_bounds__(TH, (TH == BK_THREADS && W <= 2 && DIGIT <= 10) ? 4
                 if (__lane_id() == 0) gbase = atomicAdd(o_counter, (unsigned long long)nover);
                 gbase = __shfl(gbase, 0, 64);
             }
-#pragma unroll
-            for (int q = 0; q < BK_PAIR_CHUNK; ++q) {
-                if (q >= cpl) break;
-                if ((okbits >> q) & 1u) {
-                    const uint32_t iq = idxB[pa[q]], jq = idxB[pb[q]];
-                    const uint32_t lo2 = (iq < jq ? iq : jq) - o_off;
-                    const uint32_t hi3 = (iq < jq ? jq : iq) - o_off;
-                    if (slot < (uint32_t)BK_OUT) {
-                        obuf[slot] = make_uint2(lo2, hi3);
-                    } else {
-                        const unsigned long long g = gbase + (slot - first_out);
-                        if (g < o_cap) *reinterpret_cast<uint2*>(o_pairs + 2 * g) = make_uint2(lo2, hi3);
+            if (okbits) {
+                int r2 = r_0, a2 = a_0, b2 = b_0, L2 = L_0, s2 = s_0;
+                for (int q = 0; q < nq && (okbits >> q) != 0u; ++q) {
+                    if ((okbits >> q) & 1u) {
+                        const uint32_t iq = idxB[min(s2 + a2, CAP - 1)], jq = idxB[min(s2 + b2, CAP - 1)];
+                        const uint32_t lo2 = (iq < jq ? iq : jq) - o_off;
+                        const uint32_t hi3 = (iq < jq ? jq : iq) - o_off;
+                        if (slot < (uint32_t)BK_OUT) {
+                            obuf[slot] = make_uint2(lo2, hi3);
+                        } else {
+                            const unsigned long long g = gbase + (slot - first_out);
+                            if (g < o_cap) *reinterpret_cast<uint2*>(o_pairs + 2 * g) = make_uint2(lo2, hi3);
+                        }
+                        ++slot;
                     }
-                    ++slot;
+                    advance(r2, a2, b2, L2, s2);
                 }
             }
             if (t0 + TH * (uint32_t)cpl < P) out.maybe_flush(BK_OUT / 2);
