@@ -54,7 +54,7 @@ constexpr int BK_THREADS = 256;
 constexpr int BK_WAVES = BK_THREADS / 64;
 constexpr int BK_MAXB = 4;                        // 64-element batches per wave
 constexpr int BK_CAP = BK_WAVES * 64 * BK_MAXB;   // largest bucket sorted in LDS
-constexpr int BK_PAIR_MAX = 32;                   // consecutive pairs per lane and round, at most
+constexpr int BK_PAIR_MAX = 64;                   // consecutive pairs per lane and round, at most
 constexpr int BK_GROUP = 2;                       // buckets per workgroup
 constexpr int BK_OUT = 512;                       // staged output pairs per workgroup
 constexpr int BK_DIGIT = 10;                      // mix bits counted inside a bucket
@@ -1021,7 +1021,7 @@ __global__ __launch_bounds__(TH, (TH == BK_THREADS && W <= 2 && DIGIT <= 10) ? 4
                 nq = (int)min((uint32_t)cpl, P - t);
             }
             const int r_0 = r, a_0 = a, b_0 = bb, L_0 = L, s_0 = s0;
-            uint32_t okbits = 0;
+            uint64_t okbits = 0;
             {
                 // the next candidate's strings are requested before the
                 // current one is tested (positions are clamped to the
@@ -1046,7 +1046,7 @@ __global__ __launch_bounds__(TH, (TH == BK_THREADS && W <= 2 && DIGIT <= 10) ? 4
                     }
                     const bool ok =
                         pair_ok_fast<W, HM, GT>(sa, sb, p, keep, hm, nhi, hi_rest, bmask, hi, dtabL, dtabG, bmL);
-                    okbits |= (uint32_t)ok << q;
+                    okbits |= (uint64_t)ok << q;
 #pragma unroll
                     for (int w = 0; w < W; ++w) {
                         sa[w] = na[w];
@@ -1058,15 +1058,15 @@ __global__ __launch_bounds__(TH, (TH == BK_THREADS && W <= 2 && DIGIT <= 10) ? 4
             if (p.rep > 0 && okbits) {
                 int r2 = r_0, a2 = a_0, b2 = b_0, L2 = L_0, s2 = s_0;
                 for (int q = 0; q < nq; ++q) {
-                    if (((okbits >> q) & 1u) &&
+                    if (((okbits >> q) & 1ull) &&
                         !far_in_earlier<W>(p, idxB[min(s2 + a2, CAP - 1)], idxB[min(s2 + b2, CAP - 1)]))
-                        okbits &= ~(1u << q);
+                        okbits &= ~(1ull << q);
                     advance(r2, a2, b2, L2, s2);
                 }
             }
             // one append per lane per round: wave prefix of the counts, one
             // LDS atomic per wave
-            const uint32_t nmine = (uint32_t)__popc(okbits);
+            const uint32_t nmine = (uint32_t)__popcll(okbits);
             const uint32_t incl = msm::wave_incl_scan(nmine);
             const uint32_t wtot = __shfl(incl, 63, 64);
             uint32_t wbase = 0;
@@ -1086,8 +1086,8 @@ __global__ __launch_bounds__(TH, (TH == BK_THREADS && W <= 2 && DIGIT <= 10) ? 4
             }
             if (okbits) {
                 int r2 = r_0, a2 = a_0, b2 = b_0, L2 = L_0, s2 = s_0;
-                for (int q = 0; q < nq && (okbits >> q) != 0u; ++q) {
-                    if ((okbits >> q) & 1u) {
+                for (int q = 0; q < nq && (okbits >> q) != 0ull; ++q) {
+                    if ((okbits >> q) & 1ull) {
                         const uint32_t iq = idxB[min(s2 + a2, CAP - 1)], jq = idxB[min(s2 + b2, CAP - 1)];
                         const uint32_t lo2 = (iq < jq ? iq : jq) - o_off;
                         const uint32_t hi3 = (iq < jq ? jq : iq) - o_off;
