@@ -54,7 +54,7 @@ constexpr int BK_THREADS = 256;
 constexpr int BK_WAVES = BK_THREADS / 64;
 constexpr int BK_MAXB = 4;                        // 64-element batches per wave
 constexpr int BK_CAP = BK_WAVES * 64 * BK_MAXB;   // largest bucket sorted in LDS
-constexpr int BK_PAIR_MAX = 64;                   // consecutive pairs per lane and round, at most
+constexpr int BK_PAIR_MAX = 128;                  // consecutive pairs per lane and round, at most
 constexpr int BK_GROUP = 2;                       // buckets per workgroup
 constexpr int BK_OUT = 512;                       // staged output pairs per workgroup
 constexpr int BK_DIGIT = 10;                      // mix bits counted inside a bucket
@@ -973,11 +973,12 @@ __global__ __launch_bounds__(TH, (TH == BK_THREADS && W <= 2 && DIGIT <= 10) ? 4
 
         // Flat loop over all claimed pairs (a < b), row-major per run. Each
         // lane walks cpl consecutive pairs: as few as spread P over the
-        // workgroup, at most BK_PAIR_MAX, so that most buckets take a single
+        // workgroup, at most PMAX, so that most buckets take a single
         // round with every lane busy. It keeps the results in a bit mask and
         // appends the passing pairs once per round, walking its pairs a
         // second time for their point indices.
-        const int cpl = (int)min((uint32_t)BK_PAIR_MAX, (P + TH - 1) / TH);
+        constexpr uint32_t PMAX = LIST ? BK_PAIR_MAX / 2 : BK_PAIR_MAX;  // the second pass has twice the lanes
+        const int cpl = (int)min(PMAX, (P + TH - 1) / TH);
         // next pair in row-major order over the live runs
         auto advance = [&](int& r, int& a, int& bb, int& L, int& s0) {
             ++bb;
@@ -1021,7 +1022,7 @@ __global__ __launch_bounds__(TH, (TH == BK_THREADS && W <= 2 && DIGIT <= 10) ? 4
                 nq = (int)min((uint32_t)cpl, P - t);
             }
             const int r_0 = r, a_0 = a, b_0 = bb, L_0 = L, s_0 = s0;
-            uint64_t okbits = 0;
+            uint64_t ok0 = 0, ok1 = 0;  // results of pairs 0-63 and 64-127
             {
                 // the next candidate's strings are requested before the
                 // current one is tested (positions are clamped to the
@@ -1046,7 +1047,8 @@ __global__ __launch_bounds__(TH, (TH == BK_THREADS && W <= 2 && DIGIT <= 10) ? 4
                     }
                     const bool ok =
                         pair_ok_fast<W, HM, GT>(sa, sb, p, keep, hm, nhi, hi_rest, bmask, hi, dtabL, dtabG, bmL);
-                    okbits |= (uint64_t)ok << q;
+                    if (q < 64) ok0 |= (uint64_t)ok << q;
+                    else ok1 |= (uint64_t)ok << (q - 64);
 #pragma unroll
                     for (int w = 0; w < W; ++w) {
                         sa[w] = na[w];
@@ -1055,18 +1057,21 @@ __global__ __launch_bounds__(TH, (TH == BK_THREADS && W <= 2 && DIGIT <= 10) ? 4
                 }
             }
             // point indices are read from LDS only for the pairs that pass
-            if (p.rep > 0 && okbits) {
+            auto bit_of = [&](int q) -> bool { return q < 64 ? ((ok0 >> q) & 1ull) : ((ok1 >> (q - 64)) & 1ull); };
+            if (p.rep > 0 && (ok0 | ok1)) {
                 int r2 = r_0, a2 = a_0, b2 = b_0, L2 = L_0, s2 = s_0;
                 for (int q = 0; q < nq; ++q) {
-                    if (((okbits >> q) & 1ull) &&
-                        !far_in_earlier<W>(p, idxB[min(s2 + a2, CAP - 1)], idxB[min(s2 + b2, CAP - 1)]))
-                        okbits &= ~(1ull << q);
+                    if (bit_of(q) &&
+                        !far_in_earlier<W>(p, idxB[min(s2 + a2, CAP - 1)], idxB[min(s2 + b2, CAP - 1)])) {
+                        if (q < 64) ok0 &= ~(1ull << q);
+                        else ok1 &= ~(1ull << (q - 64));
+                    }
                     advance(r2, a2, b2, L2, s2);
                 }
             }
             // one append per lane per round: wave prefix of the counts, one
             // LDS atomic per wave
-            const uint32_t nmine = (uint32_t)__popcll(okbits);
+            const uint32_t nmine = (uint32_t)(__popcll(ok0) + __popcll(ok1));
             const uint32_t incl = msm::wave_incl_scan(nmine);
             const uint32_t wtot = __shfl(incl, 63, 64);
             uint32_t wbase = 0;
@@ -1084,10 +1089,12 @@ __global__ __launch_bounds__(TH, (TH == BK_THREADS && W <= 2 && DIGIT <= 10) ? 4
                 if (__lane_id() == 0) gbase = atomicAdd(o_counter, (unsigned long long)nover);
                 gbase = __shfl(gbase, 0, 64);
             }
-            if (okbits) {
+            if (nmine) {
                 int r2 = r_0, a2 = a_0, b2 = b_0, L2 = L_0, s2 = s_0;
-                for (int q = 0; q < nq && (okbits >> q) != 0ull; ++q) {
-                    if ((okbits >> q) & 1ull) {
+                // up to the last passing pair
+                const int qend = ok1 ? 128 - __builtin_clzll(ok1) : 64 - __builtin_clzll(ok0);
+                for (int q = 0; q < qend; ++q) {
+                    if (bit_of(q)) {
                         const uint32_t iq = idxB[min(s2 + a2, CAP - 1)], jq = idxB[min(s2 + b2, CAP - 1)];
                         const uint32_t lo2 = (iq < jq ? iq : jq) - o_off;
                         const uint32_t hi3 = (iq < jq ? jq : iq) - o_off;
