@@ -12,6 +12,8 @@
 // append): eight lanes per pair balance the two at d = 128.
 #include "msm_internal.h"
 
+#include <type_traits>
+
 namespace {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
@@ -69,6 +71,7 @@ __global__ __launch_bounds__(VF_THREADS) void k_verify(const float* __restrict__
         const int64_t q = lo + team * VF_PP + pp;
         nxt[pp] = q < hi ? *reinterpret_cast<const uint2*>(pairs + 2 * q) : make_uint2(0u, 0u);
     }
+    bool check_far = true;  // wave-uniform
     for (int64_t it = 0; it < rounds; ++it) {
         const int64_t q0 = lo + (team + it * nteams) * VF_PP;
         bool live[VF_PP];
@@ -102,35 +105,68 @@ __global__ __launch_bounds__(VF_THREADS) void k_verify(const float* __restrict__
                 a2[pp] = fmaf(v, v, a2[pp]);
             }
         };
+        // Euclidean: a pair whose partial sum over the team already exceeds
+        // eps^2 is decided (each lane's FP32 sum only grows as terms are
+        // added, and so does the team's sum of them), and its remaining
+        // row pieces are not read. The check is made while at least half of
+        // the wave's pairs were rejected in its last round (far pairs);
+        // otherwise the rows are read straight through.
+        bool far[VF_PP];
+#pragma unroll
+        for (int pp = 0; pp < VF_PP; ++pp) far[pp] = false;
+        const float eps2 = eps * eps;
         if (VEC4) {
             constexpr int STEP = VF_TEAM * 4;
             constexpr int UN = 4 / VF_PP;  // row steps per pair in flight
-            int t = tl * 4;
-            for (; t + (UN - 1) * STEP < d; t += UN * STEP) {
-                floatx4 u[VF_PP][UN], v[VF_PP][UN];
+            // team-uniform steps, so that the team sum sees all lanes; lane
+            // tl takes elements tl * 4 + k * STEP in order of k
+            auto rows = [&](auto check_tag) {
+                constexpr bool CHECK = decltype(check_tag)::value;
+                int base = 0;
+                for (; base + UN * STEP <= d; base += UN * STEP) {
+                    floatx4 u[VF_PP][UN], v[VF_PP][UN];
 #pragma unroll
-                for (int pp = 0; pp < VF_PP; ++pp)
+                    for (int pp = 0; pp < VF_PP; ++pp) {
+                        if (CHECK && far[pp]) continue;
 #pragma unroll
-                    for (int r = 0; r < UN; ++r) {
-                        u[pp][r] = *reinterpret_cast<const floatx4*>(xi[pp] + t + r * STEP);
-                        v[pp][r] = *reinterpret_cast<const floatx4*>(xj[pp] + t + r * STEP);
+                        for (int r = 0; r < UN; ++r) {
+                            u[pp][r] = *reinterpret_cast<const floatx4*>(xi[pp] + base + tl * 4 + r * STEP);
+                            v[pp][r] = *reinterpret_cast<const floatx4*>(xj[pp] + base + tl * 4 + r * STEP);
+                        }
                     }
 #pragma unroll
-                for (int pp = 0; pp < VF_PP; ++pp)
+                    for (int pp = 0; pp < VF_PP; ++pp) {
+                        if (CHECK && far[pp]) continue;
 #pragma unroll
-                    for (int r = 0; r < UN; ++r)
+                        for (int r = 0; r < UN; ++r)
 #pragma unroll
-                        for (int c = 0; c < 4; ++c) acc(pp, u[pp][r][c], v[pp][r][c]);
-            }
-            for (; t < d; t += STEP) {
+                            for (int c = 0; c < 4; ++c) acc(pp, u[pp][r][c], v[pp][r][c]);
+                    }
+                    if (CHECK && base + UN * STEP < d) {
+                        bool all_far = true;
 #pragma unroll
-                for (int pp = 0; pp < VF_PP; ++pp) {
-                    const floatx4 u = *reinterpret_cast<const floatx4*>(xi[pp] + t);
-                    const floatx4 v = *reinterpret_cast<const floatx4*>(xj[pp] + t);
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) acc(pp, u[c], v[c]);
+                        for (int pp = 0; pp < VF_PP; ++pp) {
+                            if (!far[pp]) far[pp] = team_sum(a0[pp]) > eps2;
+                            all_far = all_far && far[pp];
+                        }
+                        if (all_far) break;
+                    }
                 }
-            }
+                for (int t = base + tl * 4; t < d; t += STEP) {
+#pragma unroll
+                    for (int pp = 0; pp < VF_PP; ++pp) {
+                        if (CHECK && far[pp]) continue;
+                        const floatx4 u = *reinterpret_cast<const floatx4*>(xi[pp] + t);
+                        const floatx4 v = *reinterpret_cast<const floatx4*>(xj[pp] + t);
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) acc(pp, u[c], v[c]);
+                    }
+                }
+            };
+            if (METRIC == MSM_EUCLIDEAN && check_far)
+                rows(std::true_type{});
+            else
+                rows(std::false_type{});
         } else {
 #pragma unroll
             for (int pp = 0; pp < VF_PP; ++pp) {
@@ -148,6 +184,7 @@ __global__ __launch_bounds__(VF_THREADS) void k_verify(const float* __restrict__
                 for (; t < d; t += VF_TEAM) acc(pp, xi[pp][t], xj[pp][t]);
             }
         }
+        uint32_t nlive = 0, nrej = 0;  // this round's pairs of the wave, and rejected ones
 #pragma unroll
         for (int pp = 0; pp < VF_PP; ++pp) {
             a0[pp] = team_sum(a0[pp]);
@@ -156,9 +193,9 @@ __global__ __launch_bounds__(VF_THREADS) void k_verify(const float* __restrict__
                 a2[pp] = team_sum(a2[pp]);
             }
             bool keep = false;
-            if (live[pp] && tl == 0) {
+            if (live[pp] && tl == 0 && !far[pp]) {
                 if (METRIC == MSM_EUCLIDEAN) {
-                    keep = a0[pp] <= eps * eps;
+                    keep = a0[pp] <= eps2;
                 } else {
                     const float dist = (a1[pp] == 0.f || a2[pp] == 0.f)
                                            ? 1.0f
@@ -167,7 +204,10 @@ __global__ __launch_bounds__(VF_THREADS) void k_verify(const float* __restrict__
                 }
             }
             stage.push(keep, pi[pp], pj[pp]);
+            nlive += (uint32_t)__popcll(__ballot(live[pp] && tl == 0));
+            nrej += (uint32_t)__popcll(__ballot(live[pp] && tl == 0 && !keep));
         }
+        check_far = 2 * nrej >= nlive;
         if ((it & (16 / VF_PP - 1)) == 16 / VF_PP - 1) stage.maybe_flush(VF_OUT / 2);
     }
     stage.flush();
