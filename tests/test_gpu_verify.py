@@ -110,3 +110,21 @@ def test_verify_mixed_scales(msm, ctx):
     X[1::50] *= np.float32(1e20)
     kept, _ = check(msm, ctx, X, _all_pairs(n), O.EUCLIDEAN, 0.45)
     assert kept > 0
+
+
+@pytest.mark.parametrize("d", [196, 256])
+def test_verify_early_rejection_mixed(msm, ctx, d):
+    """Rows long enough for the partial-sum rejection of far pairs (checked
+    every 64 coordinates, with a ragged tail at d = 196), on a mixture where
+    most pairs are far and cluster mates are near: the kept set is the
+    oracle's outside the rounding band, as without the early rejection."""
+    X, _ = I.gaussian_mixture(1600, d, 40, 0.02, seed=d, sigma_mode="radius")
+    pairs = _all_pairs(1600)
+    kept, _ = check(msm, ctx, X, pairs, O.EUCLIDEAN, 0.03)
+    assert 0 < kept < len(pairs) // 10
+    # a list of near pairs only, then far pairs only: the wave's mode switches
+    near = O.verify(X, pairs, O.EUCLIDEAN, 0.03)
+    head = pairs[:200_000]
+    far = head[~np.isin(codes(head), codes(near))]
+    order = np.concatenate([near, far])
+    check(msm, ctx, X, order, O.EUCLIDEAN, 0.03)
