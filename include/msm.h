@@ -352,6 +352,12 @@ typedef struct {
 /* Turn timing on (enable != 0) or off. Errors: MSM_E_INVALID for NULL ctx. */
 msm_status msm_profile_enable(msm_ctx* ctx, int32_t enable);
 
+/* Time only the kernel named `name` (as in msm_kernel_time::name) while
+ * timing is on, so that the other launches carry no events; NULL or "" times
+ * every kernel again. The name is copied. Errors: MSM_E_INVALID for NULL ctx
+ * or a name of 48 characters or more. */
+msm_status msm_profile_only(msm_ctx* ctx, const char* name);
+
 /* Wait for the recorded events and clear the totals. */
 msm_status msm_profile_reset(msm_ctx* ctx);
 

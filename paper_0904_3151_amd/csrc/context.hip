@@ -78,6 +78,7 @@ static hipEvent_t take_event(msm_ctx* ctx)
 KernelTimer::KernelTimer(msm_ctx* ctx, hipStream_t s, const char* name) : ctx_(ctx), s_(s), name_(name)
 {
     if (!ctx_->prof) return;
+    if (!ctx_->prof_only.empty() && ctx_->prof_only != name_) return;
     a_ = take_event(ctx_);
     if (a_ && hipEventRecord(a_, s_) != hipSuccess) {
         (void)hipGetLastError();
@@ -183,6 +184,16 @@ extern "C" msm_status msm_profile_enable(msm_ctx* ctx, int32_t enable)
     if (!ctx) return msm::fail(nullptr, MSM_E_INVALID, "msm_profile_enable: ctx is NULL");
     ctx->err.clear();
     ctx->prof = enable != 0;
+    return MSM_OK;
+}
+
+extern "C" msm_status msm_profile_only(msm_ctx* ctx, const char* name)
+{
+    if (!ctx) return msm::fail(nullptr, MSM_E_INVALID, "msm_profile_only: ctx is NULL");
+    ctx->err.clear();
+    if (name && std::strlen(name) >= sizeof(((msm_kernel_time*)nullptr)->name))
+        return msm::fail(ctx, MSM_E_INVALID, "msm_profile_only: name too long");
+    ctx->prof_only = name ? name : "";
     return MSM_OK;
 }
 

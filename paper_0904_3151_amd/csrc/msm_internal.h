@@ -29,6 +29,7 @@ struct msm_ctx {
     int32_t last_jblocks = 0;
     // Per-kernel timing: a pair of HIP events around every launch while on.
     bool prof = false;
+    std::string prof_only;  // when not empty, the one kernel name that is timed
     struct Pending {
         const char* name;
         hipEvent_t a, b;

@@ -45,7 +45,7 @@ EXPORTS = ("msm_version", "msm_create", "msm_destroy", "msm_last_error",
            "msm_project_mlp", "msm_mlp_loss_grad", "msm_mlp_adam", "msm_mlp_train",
            "msm_batch_create", "msm_batch_run", "msm_batch_launch_graph", "msm_batch_tuning",
            "msm_batch_destroy",
-           "msm_profile_enable", "msm_profile_reset", "msm_profile_read")
+           "msm_profile_enable", "msm_profile_only", "msm_profile_reset", "msm_profile_read")
 
 
 class KernelTime(ctypes.Structure):
@@ -131,6 +131,8 @@ def _load():
     lib.msm_batch_destroy.restype = None
     lib.msm_profile_enable.argtypes = [vp, i32]
     lib.msm_profile_enable.restype = i32
+    lib.msm_profile_only.argtypes = [vp, ctypes.c_char_p]
+    lib.msm_profile_only.restype = i32
     lib.msm_profile_reset.argtypes = [vp]
     lib.msm_profile_reset.restype = i32
     lib.msm_profile_read.argtypes = [vp, ctypes.POINTER(KernelTime), i32]
@@ -530,6 +532,11 @@ class Batch:
 
 def msm_profile_enable(ctx: Context, enable: bool = True):
     _check(ctx, _lib.msm_profile_enable(ctx.handle, int(bool(enable))))
+
+
+def msm_profile_only(ctx: Context, name: str | None):
+    """Time only kernel `name` while timing is on (None: every kernel)."""
+    _check(ctx, _lib.msm_profile_only(ctx.handle, None if name is None else name.encode()))
 
 
 def msm_profile_reset(ctx: Context):
