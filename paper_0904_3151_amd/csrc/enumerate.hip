@@ -69,9 +69,15 @@ msm_status run_enumerate(msm_ctx* ctx, const uint64_t* S, int64_t n, int ell, in
     int r1 = 0;
     while (r1 < 13 && ((int64_t)1 << r1) * TARGET_BUCKET < n) ++r1;
     const int nb = 1 << r1;
-    int T = 4096;  // points per partition tile; at most 256 tiles per combination
+    // points per partition tile (at most 256 tiles per combination); the
+    // scatter sorts a tile in LDS chunks of sch points, as many as fit
+    // beside its two words per bucket
+    int T = SCAT_THREADS * SCAT_PPT;
     while ((n + T - 1) / T > 256) T *= 2;
     const int nt = (int)((n + T - 1) / T);
+    int sch = SCAT_THREADS * SCAT_PPT;
+    while (sch > SCAT_THREADS && (size_t)sch * 8 + (size_t)nb * 8 > (size_t)150 * 1024) sch /= 2;
+    const size_t scat_lds = (size_t)sch * 8 + (size_t)nb * 8;
 
     // Combinations per launch group, bounded by scratch size.
     const size_t per_combo = msm::align_up((size_t)n * 8, 256) + msm::align_up((size_t)nt * nb * 4, 256) +
@@ -155,6 +161,7 @@ msm_status run_enumerate(msm_ctx* ctx, const uint64_t* S, int64_t n, int ell, in
     p.nb = nb;
     p.T = T;
     p.nt = nt;
+    p.sch = sch;
     p.counts = d_counts;
     p.base = d_base;
     p.part = d_part;
@@ -217,6 +224,9 @@ msm_status run_enumerate(msm_ctx* ctx, const uint64_t* S, int64_t n, int ell, in
     ctx->last_groupings = C;
     ctx->last_jblocks = hier ? jsel : 0;
 
+    if (scat_lds > 65536)  // above the default dynamic LDS limit of a launch
+        MSM_HIP(ctx, hipFuncSetAttribute(reinterpret_cast<const void*>(&k_part_scatter<W>),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)scat_lds));
     for (int rep = 0; rep < Q; ++rep) {
     p.rep = rep;
     p.S = S + (uint64_t)rep * p.rep_stride;
@@ -239,8 +249,7 @@ msm_status run_enumerate(msm_ctx* ctx, const uint64_t* S, int64_t n, int ell, in
         }
         {
             msm::KernelTimer kt(ctx, stream, "k_part_scatter");
-            hipLaunchKernelGGL((k_part_scatter<W>), dim3(part_grid), dim3(PART_THREADS), nb * sizeof(uint32_t),
-                               stream, p);
+            hipLaunchKernelGGL((k_part_scatter<W>), dim3(part_grid), dim3(SCAT_THREADS), scat_lds, stream, p);
         }
         {
             msm::KernelTimer kt(ctx, stream, "k_bucket");

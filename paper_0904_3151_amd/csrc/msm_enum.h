@@ -49,6 +49,8 @@ namespace {
 constexpr int MAXW = 4;
 constexpr int MAXK = 64;
 constexpr int PART_THREADS = 256;
+constexpr int SCAT_THREADS = 1024;  // scatter: threads, and points per thread in a chunk
+constexpr int SCAT_PPT = 16;
 constexpr int SCAN_THREADS = 1024;
 constexpr int BK_THREADS = 256;
 constexpr int BK_WAVES = BK_THREADS / 64;
@@ -107,6 +109,7 @@ struct Params {
     int r1;                  // bucket bits (top bits of the mix)
     int nb;                  // 1 << r1
     int T, nt;               // partition tile size and count
+    int sch;                 // points per sorted scatter chunk (at most SCAT_THREADS * SCAT_PPT)
     int units;               // combinations of the group x tiles
     uint32_t* counts;        // [c][t][b] tile counts, then tile offsets
     uint32_t* base;          // [c][nb + 1] bucket starts
@@ -290,28 +293,88 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_part_scan(Params p)
     if (threadIdx.x == 0) base[p.nb] = (uint32_t)p.n;
 }
 
+// Scatter of one tile in chunks of p.sch points: the chunk is counting-
+// sorted by bucket in LDS (its points' buckets counted, the counts scanned,
+// the entries placed), then written out in that order, so consecutive
+// threads write consecutive entries of one bucket. With 4096-point tiles a
+// tile holds about two points per bucket and nearly every 8-byte write is a
+// partial line; sorted chunks of 16384 points write runs of about eight.
+// SCAT_THREADS threads; dynamic LDS: sch entries, then 2 * nb words.
 template <int W>
-__global__ __launch_bounds__(PART_THREADS) void k_part_scatter(Params p)
+__global__ __launch_bounds__(SCAT_THREADS) void k_part_scatter(Params p)
 {
-    extern __shared__ uint32_t cursor[];
+    extern __shared__ unsigned long long scat_lds[];
+    __shared__ uint32_t wsum[SCAT_THREADS / 64];
     int cl, t;
     if (!xcd_unit(p.units, cl, t, p.nt)) return;
+    uint64_t* staged = reinterpret_cast<uint64_t*>(scat_lds);  // p.sch entries
+    uint32_t* lcnt = reinterpret_cast<uint32_t*>(staged + p.sch);  // chunk counts, then starts
+    uint32_t* gb = lcnt + p.nb;                                    // next global slot per bucket
     uint64_t keep[W];
     load_keep<W>(p.combos + cl, keep);
     const uint32_t* off = p.counts + ((size_t)cl * p.nt + t) * p.nb;
     const uint32_t* base = p.base + (size_t)cl * (p.nb + 1);
-    for (int b = threadIdx.x; b < p.nb; b += PART_THREADS) cursor[b] = base[b] + off[b];
-    __syncthreads();
+    for (int b = threadIdx.x; b < p.nb; b += SCAT_THREADS) gb[b] = base[b] + off[b];
     uint64_t* part = p.part + (size_t)cl * p.n;
-    const int64_t beg = (int64_t)t * p.T;
-    const int64_t end = min(p.n, beg + p.T);
-    for (int64_t i = beg + threadIdx.x; i < end; i += PART_THREADS) {
-        uint64_t s[W];
-        load_string<W>(p.S, (uint64_t)i, s);
-        const uint32_t mx = masked_mix<W>(s, keep);
-        const uint32_t b = p.r1 ? (mx >> (32 - p.r1)) : 0u;
-        const uint32_t pos = atomicAdd(&cursor[b], 1u);
-        part[pos] = ((uint64_t)mx << 32) | (uint64_t)(uint32_t)i;
+    const int shift = 32 - p.r1;
+    const int64_t tbeg = (int64_t)t * p.T;
+    const int64_t tend = min(p.n, tbeg + p.T);
+    for (int64_t beg = tbeg; beg < tend; beg += p.sch) {
+        const int cnt = (int)min<int64_t>(p.sch, tend - beg);
+        for (int b = threadIdx.x; b < p.nb; b += SCAT_THREADS) lcnt[b] = 0;
+        __syncthreads();  // lcnt is zero, gb is set, staged is free
+        uint32_t mx[SCAT_PPT], rk[SCAT_PPT];
+#pragma unroll
+        for (int k = 0; k < SCAT_PPT; ++k) {
+            const int e = (int)threadIdx.x + k * SCAT_THREADS;
+            mx[k] = 0u;
+            rk[k] = 0u;
+            if (e < cnt) {
+                uint64_t s[W];
+                load_string<W>(p.S, (uint64_t)(beg + e), s);
+                mx[k] = masked_mix<W>(s, keep);
+                rk[k] = atomicAdd(&lcnt[p.r1 ? (mx[k] >> shift) : 0u], 1u);
+            }
+        }
+        __syncthreads();
+        // exclusive scan of the chunk's bucket counts: each thread a run of
+        // consecutive buckets, a wave scan of the run sums, then the waves
+        const int per = (p.nb + SCAT_THREADS - 1) / SCAT_THREADS;
+        const int b0 = (int)threadIdx.x * per, b1 = min(p.nb, b0 + per);
+        uint32_t sum = 0;
+        for (int b = b0; b < b1; ++b) sum += lcnt[b];
+        const uint32_t incl = msm::wave_incl_scan(sum);
+        if ((threadIdx.x & 63) == 63) wsum[threadIdx.x >> 6] = incl;
+        __syncthreads();
+        uint32_t run = incl - sum;
+        for (int w = 0; w < (int)(threadIdx.x >> 6); ++w) run += wsum[w];
+        for (int b = b0; b < b1; ++b) {
+            const uint32_t c = lcnt[b];
+            lcnt[b] = run;
+            run += c;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < SCAT_PPT; ++k) {
+            const int e = (int)threadIdx.x + k * SCAT_THREADS;
+            if (e < cnt) {
+                const uint32_t b = p.r1 ? (mx[k] >> shift) : 0u;
+                staged[lcnt[b] + rk[k]] = ((uint64_t)mx[k] << 32) | (uint64_t)(uint32_t)(beg + e);
+            }
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < cnt; e += SCAT_THREADS) {
+            const uint64_t v = staged[e];
+            const uint32_t b = p.r1 ? ((uint32_t)(v >> 32) >> shift) : 0u;
+            part[gb[b] + (uint32_t)e - lcnt[b]] = v;
+        }
+        __syncthreads();  // every read of gb and lcnt is done
+        // the next chunk's entries of a bucket follow this chunk's
+        for (int b = threadIdx.x; b < p.nb; b += SCAT_THREADS) {
+            const uint32_t next = (b + 1 < p.nb ? lcnt[b + 1] : (uint32_t)cnt);
+            gb[b] += next - lcnt[b];
+        }
+        __syncthreads();  // lcnt is read before the next chunk clears it
     }
 }
 
