@@ -28,9 +28,10 @@ struct Config {
     int group;   // buckets per workgroup
 };
 
-constexpr int BATCH_T = 4096;        // points per partition tile
+constexpr int BATCH_T = 4096;        // points per partition tile (PART_THREADS * BPART_PPT)
 constexpr int MAX_R = 13;            // at most 8192 buckets per instance
 constexpr int PROJ_ENTRY_TILES = 4;  // projection tiles per entry
+static_assert(BATCH_T <= PART_THREADS * BPART_PPT, "a partition tile must fit the scatter's registers");
 
 int bits_for(int64_t n, int target)
 {
@@ -232,7 +233,7 @@ msm_status enqueue_enumerate(msm_batch& b, int64_t* m_dev, hipStream_t s, bool t
             kt.reset();
             if (prof) kt.reset(new msm::KernelTimer(ctx, s, "k_bpart_scatter"));
             hipLaunchKernelGGL((k_bpart_scatter<W>), dim3(part_grid), dim3(PART_THREADS),
-                               b.max_nbi * sizeof(uint32_t), s, p, ba);
+                               (size_t)BATCH_T * 8 + (size_t)b.max_nbi * 8, s, p, ba, b.max_nbi);
             kt.reset();
             if (prof) kt.reset(new msm::KernelTimer(ctx, s, "k_bucket_batch"));
             launch_bucket_digit<W>(p, ba, b.cfg.digit, b.NB, cc, s);
@@ -466,6 +467,15 @@ extern "C" msm_status msm_batch_create(msm_ctx* ctx, const msm_instance* inst, i
     MSM_HIP(ctx, hipMemcpy(b->d_combos, b->combos.data(), sizeof(Combo) * b->C, hipMemcpyHostToDevice));
     MSM_HIP(ctx, hipMemcpy(b->d_bm, b->bm.data(), sizeof(uint64_t) * b->bm.size(), hipMemcpyHostToDevice));
     MSM_HIP(ctx, hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+    {
+        // the partition scatter stages a whole tile and two words per bucket in LDS
+        const int lds = BATCH_T * 8 + (1 << MAX_R) * 8;
+        const void* f = b->W == 1   ? reinterpret_cast<const void*>(&k_bpart_scatter<1>)
+                        : b->W == 2 ? reinterpret_cast<const void*>(&k_bpart_scatter<2>)
+                        : b->W == 3 ? reinterpret_cast<const void*>(&k_bpart_scatter<3>)
+                                    : reinterpret_cast<const void*>(&k_bpart_scatter<4>);
+        MSM_HIP(ctx, hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+    }
 
     st = set_config(*b, Config{512, 10, 8});
     if (st != MSM_OK) return st;

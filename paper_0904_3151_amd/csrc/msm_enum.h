@@ -51,6 +51,7 @@ constexpr int MAXK = 64;
 constexpr int PART_THREADS = 256;
 constexpr int SCAT_THREADS = 1024;  // scatter: threads, and points per thread in a chunk
 constexpr int SCAT_PPT = 16;
+constexpr int BPART_PPT = 16;       // points per thread of a batched partition tile (PART_THREADS threads)
 constexpr int SCAN_THREADS = 1024;
 constexpr int BK_THREADS = 256;
 constexpr int BK_WAVES = BK_THREADS / 64;
@@ -454,30 +455,76 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_bpart_scan(Params p, BatchArgs
     if (threadIdx.x == 0) base[nbi] = (uint32_t)(in.off + in.n);
 }
 
+// As k_part_scatter, one tile (p.T <= PART_THREADS * BPART_PPT points) at a
+// time: sorted by bucket in LDS, then written in bucket runs. Dynamic LDS:
+// p.T entries, then 2 * (the largest instance bucket count) words.
 template <int W>
-__global__ __launch_bounds__(PART_THREADS) void k_bpart_scatter(Params p, BatchArgs ba)
+__global__ __launch_bounds__(PART_THREADS) void k_bpart_scatter(Params p, BatchArgs ba, int max_nbi)
 {
-    extern __shared__ uint32_t cursor[];
+    extern __shared__ unsigned long long bscat_lds[];
+    __shared__ uint32_t wsum[PART_THREADS / 64];
     int cl, t;
     if (!xcd_unit(p.units, cl, t, p.nt)) return;
     const BInst& in = ba.inst[ba.tile_inst[t]];
     const int r = in.r;
     const int nbi = 1 << r;
+    uint64_t* staged = reinterpret_cast<uint64_t*>(bscat_lds);
+    uint32_t* lcnt = reinterpret_cast<uint32_t*>(staged + p.T);
+    uint32_t* gb = lcnt + max_nbi;
     uint64_t keep[W];
     load_keep<W>(p.combos + cl, keep);
     const uint32_t* off = p.counts + (size_t)cl * ba.cnt_stride + in.cnt_off + (size_t)(t - in.tstart) * nbi;
     const uint32_t* base = p.base + (size_t)cl * (p.nb + 1) + in.bstart;
-    for (int b = threadIdx.x; b < nbi; b += PART_THREADS) cursor[b] = base[b] + off[b];
+    for (int b = threadIdx.x; b < nbi; b += PART_THREADS) {
+        gb[b] = base[b] + off[b];
+        lcnt[b] = 0;
+    }
     __syncthreads();
     uint64_t* part = p.part + (size_t)cl * p.n;
     const int64_t beg = (int64_t)in.off + (int64_t)(t - in.tstart) * p.T;
-    const int64_t end = min((int64_t)(in.off + in.n), beg + p.T);
-    for (int64_t i = beg + threadIdx.x; i < end; i += PART_THREADS) {
-        uint64_t s[W];
-        load_string<W>(p.S, (uint64_t)i, s);
-        const uint32_t mx = masked_mix<W>(s, keep);
-        const uint32_t pos = atomicAdd(&cursor[r ? (mx >> (32 - r)) : 0u], 1u);
-        part[pos] = ((uint64_t)mx << 32) | (uint64_t)(uint32_t)i;
+    const int cnt = (int)min<int64_t>(p.T, (int64_t)(in.off + in.n) - beg);
+    uint32_t mx[BPART_PPT], rk[BPART_PPT];
+#pragma unroll
+    for (int k = 0; k < BPART_PPT; ++k) {
+        const int e = (int)threadIdx.x + k * PART_THREADS;
+        mx[k] = 0u;
+        rk[k] = 0u;
+        if (e < cnt) {
+            uint64_t s[W];
+            load_string<W>(p.S, (uint64_t)(beg + e), s);
+            mx[k] = masked_mix<W>(s, keep);
+            rk[k] = atomicAdd(&lcnt[r ? (mx[k] >> (32 - r)) : 0u], 1u);
+        }
+    }
+    __syncthreads();
+    const int per = (nbi + PART_THREADS - 1) / PART_THREADS;
+    const int b0 = (int)threadIdx.x * per, b1 = min(nbi, b0 + per);
+    uint32_t sum = 0;
+    for (int b = b0; b < b1; ++b) sum += lcnt[b];
+    const uint32_t incl = msm::wave_incl_scan(sum);
+    if ((threadIdx.x & 63) == 63) wsum[threadIdx.x >> 6] = incl;
+    __syncthreads();
+    uint32_t run = incl - sum;
+    for (int w = 0; w < (int)(threadIdx.x >> 6); ++w) run += wsum[w];
+    for (int b = b0; b < b1; ++b) {
+        const uint32_t c = lcnt[b];
+        lcnt[b] = run;
+        run += c;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < BPART_PPT; ++k) {
+        const int e = (int)threadIdx.x + k * PART_THREADS;
+        if (e < cnt) {
+            const uint32_t b = r ? (mx[k] >> (32 - r)) : 0u;
+            staged[lcnt[b] + rk[k]] = ((uint64_t)mx[k] << 32) | (uint64_t)(uint32_t)(beg + e);
+        }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < cnt; e += PART_THREADS) {
+        const uint64_t v = staged[e];
+        const uint32_t b = r ? ((uint32_t)(v >> 32) >> (32 - r)) : 0u;
+        part[gb[b] + (uint32_t)e - lcnt[b]] = v;
     }
 }
 
