@@ -17,6 +17,7 @@
 // every candidate on the batch itself.
 #include "msm_enum.h"
 
+#include <algorithm>
 #include <cstring>
 #include <memory>
 
@@ -30,7 +31,7 @@ struct Config {
 
 constexpr int BATCH_T = 4096;        // points per partition tile (PART_THREADS * BPART_PPT)
 constexpr int MAX_R = 13;            // at most 8192 buckets per instance
-constexpr int PROJ_ENTRY_TILES = 4;  // projection tiles per entry
+constexpr int PROJ_ENTRY_ROWS = 1024;  // rows per projection entry (a multiple of the tile)
 static_assert(BATCH_T <= PART_THREADS * BPART_PPT, "a partition tile must fit the scatter's registers");
 
 int bits_for(int64_t n, int target)
@@ -72,6 +73,7 @@ struct msm_batch {
     uint32_t* d_ovfc = nullptr;
     uint64_t* d_tile0 = nullptr;
     unsigned long long* d_work = nullptr;
+    uint32_t* d_pwork = nullptr;  // entry counter of the projection
 
     // current configuration
     Config cfg{512, 10, 8};
@@ -265,8 +267,9 @@ msm_status enqueue(msm_batch& b, int64_t* m_dev, hipStream_t s, bool timed)
     if (b.npent > 0) {
         std::unique_ptr<msm::KernelTimer> kt;
         if (timed && ctx->prof) kt.reset(new msm::KernelTimer(ctx, s, "k_project_batch"));
-        const int grid = std::min(b.npent, 2 * ctx->num_cu);
-        MSM_HIP(ctx, msm::batch_project(b.d_pinst, b.d_pent, b.npent, b.ell, b.max_d, grid, s));
+        const int grid = std::min(b.npent, 4 * ctx->num_cu);
+        hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, b.d_pwork, 1);
+        MSM_HIP(ctx, msm::batch_project(b.d_pinst, b.d_pent, b.npent, b.ell, b.max_d, grid, b.d_pwork, s));
     }
     switch (b.W) {
         case 1: return enqueue_enumerate<1>(b, m_dev, s, timed);
@@ -391,7 +394,7 @@ extern "C" msm_status msm_batch_create(msm_ctx* ctx, const msm_instance* inst, i
     // projection entries: runs of whole tiles of one instance
     std::vector<msm::ProjInst> pinst(count);
     std::vector<msm::ProjEntry> pent;
-    const int rows_per_entry = msm::batch_project_rows(ell) * PROJ_ENTRY_TILES;
+    const int rows_per_entry = std::max(PROJ_ENTRY_ROWS, msm::batch_project_rows(ell));
     for (int i = 0; i < count; ++i) {
         const msm_instance& e = inst[i];
         msm::ProjInst& q = pinst[i];
@@ -405,6 +408,10 @@ extern "C" msm_status msm_batch_create(msm_ctx* ctx, const msm_instance* inst, i
         for (int64_t r0 = 0; r0 < e.n; r0 += rows_per_entry)
             pent.push_back(msm::ProjEntry{r0, (int32_t)std::min<int64_t>(rows_per_entry, e.n - r0), (uint32_t)i});
     }
+    // costliest entries first: claimed in this order, they even out at the end
+    std::stable_sort(pent.begin(), pent.end(), [&](const msm::ProjEntry& x, const msm::ProjEntry& y) {
+        return (int64_t)x.rows * inst[x.inst].d > (int64_t)y.rows * inst[y.inst].d;
+    });
     b->npent = (int)pent.size();
 
     // sizes: the smallest bucket target has the most buckets
@@ -434,6 +441,7 @@ extern "C" msm_status msm_batch_create(msm_ctx* ctx, const msm_instance* inst, i
     cv.take<uint32_t>(4);
     cv.take<uint64_t>((size_t)Cg * zs.NB + 1);
     cv.take<unsigned long long>(1);
+    cv.take<uint32_t>(1);
     {
         const hipError_t e = hipMalloc(&b->mem, cv.off);
         if (e != hipSuccess) {
@@ -460,6 +468,7 @@ extern "C" msm_status msm_batch_create(msm_ctx* ctx, const msm_instance* inst, i
     b->d_ovfc = c2.take<uint32_t>(4);
     b->d_tile0 = c2.take<uint64_t>((size_t)Cg * zs.NB + 1);
     b->d_work = c2.take<unsigned long long>(1);
+    b->d_pwork = c2.take<uint32_t>(1);
     for (int i = 0; i < count; ++i) pinst[i].S2 = b->d_S + (size_t)b->off[i] * b->W;
     MSM_HIP(ctx, hipMemcpy(b->d_pinst, pinst.data(), sizeof(msm::ProjInst) * count, hipMemcpyHostToDevice));
     if (!pent.empty())

@@ -88,9 +88,10 @@ struct ProjEntry {    // a run of rows of one instance
 // should hold a multiple of it).
 int batch_project_rows(int ell);
 // Enqueues the batched projection over `nentries` entries with a grid of
-// `grid` persistent workgroups; max_d bounds every instance's d.
+// `grid` persistent workgroups that claim entries from *work (which must be
+// zero when the kernel starts); max_d bounds every instance's d.
 hipError_t batch_project(const ProjInst* inst, const ProjEntry* entries, int nentries, int ell, int max_d, int grid,
-                         hipStream_t stream);
+                         unsigned int* work, hipStream_t stream);
 
 // Carves consecutive 256-byte-aligned pieces out of one scratch buffer.
 struct Carver {

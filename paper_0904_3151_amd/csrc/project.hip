@@ -165,23 +165,31 @@ __global__ __launch_bounds__(PJ_THREADS) void k_project_f32(
         project_tile<NCB, RB>(X, tile * ROWS_PER_TILE, n, d, ldx, R, ell, S, nullptr, W, kt_rows, nkt, vec4, Rl);
 }
 
-// Batched projection: workgroups take entries (a run of rows of one
-// instance) in turn; R of the entry's instance is staged once per entry.
+// Batched projection: workgroups claim entries (a run of rows of one
+// instance) from a counter (*work, zero at launch), so that entries of
+// different d even out; R of the entry's instance is staged once per entry,
+// only as deep as its d.
 template <int NCB, int RB>
 __global__ __launch_bounds__(PJ_THREADS) void k_project_batch(const msm::ProjInst* __restrict__ inst,
                                                               const msm::ProjEntry* __restrict__ entries,
-                                                              int nentries, int ell, int W, int kt_rows)
+                                                              int nentries, int ell, int W, int kt_rows,
+                                                              unsigned int* __restrict__ work)
 {
     extern __shared__ floatx4 Rl[];
+    __shared__ int s_entry;
     constexpr int ROWS_PER_TILE = PJ_WAVES * RB * 16;
-    for (int e = blockIdx.x; e < nentries; e += gridDim.x) {
+    for (;;) {
+        __syncthreads();  // the previous entry is done with Rl and s_entry
+        if (threadIdx.x == 0) s_entry = (int)atomicAdd(work, 1u);
+        __syncthreads();
+        const int e = s_entry;
+        if (e >= nentries) break;
         const msm::ProjEntry en = entries[e];
         const msm::ProjInst& in = inst[en.inst];
         const int d = in.d;
         const int nkt = (d + kt_rows - 1) / kt_rows;
         if (nkt == 1) {
-            __syncthreads();  // the previous entry is done with Rl
-            stage_r<NCB>(Rl, in.R, d, ell, 0, kt_rows / 16);
+            stage_r<NCB>(Rl, in.R, d, ell, 0, (d + 15) / 16);
             __syncthreads();
         }
         const int64_t end = en.row0 + en.rows;
@@ -254,18 +262,23 @@ extern "C" msm_status msm_project(msm_ctx* ctx, const float* X, int64_t n, int32
 
 namespace {
 
+// Row blocks per wave of the batched projection (measured on the batched
+// mix of d = 32, 64 and 128: at ell <= 64 one block per wave and more
+// workgroups per CU beat the single projection's four blocks).
+constexpr int batch_rb(int ncb) { return ncb <= 4 ? 1 : (ncb <= 8 ? 2 : 1); }
+
 template <int NCB>
 hipError_t launch_batch(const msm::ProjInst* inst, const msm::ProjEntry* entries, int nentries, int ell,
-                        int max_d, int grid, hipStream_t stream)
+                        int max_d, int grid, unsigned int* work, hipStream_t stream)
 {
-    constexpr int RB = NCB <= 4 ? 4 : (NCB <= 8 ? 2 : 1);
+    constexpr int RB = batch_rb(NCB);
     const int W = (ell + 63) / 64;
     const int dpad = (max_d + 15) / 16 * 16;
     const int max_chunks = PJ_LDS_BYTES / (NCB * 64 * 16);
     const int kt_rows = min(dpad, max_chunks * 16);
     const size_t lds = (size_t)(kt_rows / 16) * NCB * 64 * sizeof(floatx4);
     hipLaunchKernelGGL((k_project_batch<NCB, RB>), dim3((unsigned)grid), dim3(PJ_THREADS), lds, stream, inst,
-                       entries, nentries, ell, W, kt_rows);
+                       entries, nentries, ell, W, kt_rows, work);
     return hipGetLastError();
 }
 
@@ -276,29 +289,29 @@ namespace msm {
 int batch_project_rows(int ell)
 {
     const int ncb = (ell + 15) / 16;
-    return PJ_WAVES * 16 * (ncb <= 4 ? 4 : (ncb <= 8 ? 2 : 1));
+    return PJ_WAVES * 16 * batch_rb(ncb);
 }
 
 hipError_t batch_project(const ProjInst* inst, const ProjEntry* entries, int nentries, int ell, int max_d, int grid,
-                         hipStream_t stream)
+                         unsigned int* work, hipStream_t stream)
 {
     switch ((ell + 15) / 16) {
-        case 1: return launch_batch<1>(inst, entries, nentries, ell, max_d, grid, stream);
-        case 2: return launch_batch<2>(inst, entries, nentries, ell, max_d, grid, stream);
-        case 3: return launch_batch<3>(inst, entries, nentries, ell, max_d, grid, stream);
-        case 4: return launch_batch<4>(inst, entries, nentries, ell, max_d, grid, stream);
-        case 5: return launch_batch<5>(inst, entries, nentries, ell, max_d, grid, stream);
-        case 6: return launch_batch<6>(inst, entries, nentries, ell, max_d, grid, stream);
-        case 7: return launch_batch<7>(inst, entries, nentries, ell, max_d, grid, stream);
-        case 8: return launch_batch<8>(inst, entries, nentries, ell, max_d, grid, stream);
-        case 9: return launch_batch<9>(inst, entries, nentries, ell, max_d, grid, stream);
-        case 10: return launch_batch<10>(inst, entries, nentries, ell, max_d, grid, stream);
-        case 11: return launch_batch<11>(inst, entries, nentries, ell, max_d, grid, stream);
-        case 12: return launch_batch<12>(inst, entries, nentries, ell, max_d, grid, stream);
-        case 13: return launch_batch<13>(inst, entries, nentries, ell, max_d, grid, stream);
-        case 14: return launch_batch<14>(inst, entries, nentries, ell, max_d, grid, stream);
-        case 15: return launch_batch<15>(inst, entries, nentries, ell, max_d, grid, stream);
-        default: return launch_batch<16>(inst, entries, nentries, ell, max_d, grid, stream);
+        case 1: return launch_batch<1>(inst, entries, nentries, ell, max_d, grid, work, stream);
+        case 2: return launch_batch<2>(inst, entries, nentries, ell, max_d, grid, work, stream);
+        case 3: return launch_batch<3>(inst, entries, nentries, ell, max_d, grid, work, stream);
+        case 4: return launch_batch<4>(inst, entries, nentries, ell, max_d, grid, work, stream);
+        case 5: return launch_batch<5>(inst, entries, nentries, ell, max_d, grid, work, stream);
+        case 6: return launch_batch<6>(inst, entries, nentries, ell, max_d, grid, work, stream);
+        case 7: return launch_batch<7>(inst, entries, nentries, ell, max_d, grid, work, stream);
+        case 8: return launch_batch<8>(inst, entries, nentries, ell, max_d, grid, work, stream);
+        case 9: return launch_batch<9>(inst, entries, nentries, ell, max_d, grid, work, stream);
+        case 10: return launch_batch<10>(inst, entries, nentries, ell, max_d, grid, work, stream);
+        case 11: return launch_batch<11>(inst, entries, nentries, ell, max_d, grid, work, stream);
+        case 12: return launch_batch<12>(inst, entries, nentries, ell, max_d, grid, work, stream);
+        case 13: return launch_batch<13>(inst, entries, nentries, ell, max_d, grid, work, stream);
+        case 14: return launch_batch<14>(inst, entries, nentries, ell, max_d, grid, work, stream);
+        case 15: return launch_batch<15>(inst, entries, nentries, ell, max_d, grid, work, stream);
+        default: return launch_batch<16>(inst, entries, nentries, ell, max_d, grid, work, stream);
     }
 }
 
