@@ -224,3 +224,53 @@ def test_per_combination_field_layouts(msm, ctx, ell, k, h):
     assert check(msm, ctx, S, ell, k, h) > 0
     g, j = msm.msm_enumerate_last_plan(ctx)
     assert j == 0 and g == math.comb(k, h)
+
+
+def clustered_strings_fast(n, ell, n_seeds, flips, seed):
+    """Clustered strings for millions of rows: the first n_seeds rows are
+    uniform, every other row copies a random seed row and flips up to
+    `flips` positions (each of `flips` draws applied with probability 1/2;
+    a repeated position flips back). Rows are shuffled."""
+    rng = np.random.default_rng(seed)
+    W = (ell + 63) // 64
+    S = rng.integers(0, np.iinfo(np.uint64).max, size=(n, W), dtype=np.uint64, endpoint=True)
+    if ell % 64:
+        S[:, -1] &= np.uint64((1 << (ell % 64)) - 1)
+    parents = rng.integers(0, n_seeds, size=n - n_seeds)
+    S[n_seeds:] = S[parents]
+    rows_all = np.arange(n_seeds, n)
+    for _ in range(flips):
+        pos = rng.integers(0, ell, size=n - n_seeds)
+        on = rng.random(n - n_seeds) < 0.5
+        r, p = rows_all[on], pos[on]
+        S[r, p // 64] ^= np.left_shift(np.uint64(1), (p % 64).astype(np.uint64))
+    return S[rng.permutation(n)]
+
+
+def test_enumerate_most_buckets_sampled_rows(msm, ctx):
+    """4.3M clustered strings take the largest partition (8192 buckets, so the
+    scatter sorts each tile in several LDS chunks and every thread scans
+    several bucket counts). Whole-output invariants, and every Hamming partner
+    of sampled rows against the oracle's exhaustive search over all n."""
+    n, ell, k, h = 4_300_000, 128, 8, 4
+    S_np = clustered_strings_fast(n, ell, n // 8, 6, seed=4301)
+    announce("enumerate most buckets", n, ell, k, h)
+    S = torch.from_numpy(S_np.view(np.int64)).cuda()
+    P, m = msm.enumerate_pairs(ctx, S, ell, k, h, cap_hint=1 << 25)
+    torch.cuda.synchronize()
+    assert m > 0 and P.shape == (m, 2)
+    i = P[:, 0].to(torch.int64)
+    j = P[:, 1].to(torch.int64)
+    assert bool((i < j).all()) and bool((i >= 0).all()) and bool((j < n).all())
+    c, _ = torch.sort(i * n + j)
+    assert not bool((c[1:] == c[:-1]).any()), "duplicate pairs"
+    del c
+    rows = I.subsample_indices(n, 64, seed=4302)
+    want = codes(O.hamming_partners(S_np, h, rows))
+    rt = torch.from_numpy(rows).cuda()
+    sel = torch.isin(i, rt) | torch.isin(j, rt)
+    got = codes(to_np_pairs(P[sel].contiguous()))
+    assert len(want) > 0
+    assert np.array_equal(got, want), (len(got), len(want))
+    del S, P, i, j
+    torch.cuda.empty_cache()
