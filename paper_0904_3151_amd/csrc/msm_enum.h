@@ -58,6 +58,7 @@ constexpr int BK_WAVES = BK_THREADS / 64;
 constexpr int BK_MAXB = 4;                        // 64-element batches per wave
 constexpr int BK_CAP = BK_WAVES * 64 * BK_MAXB;   // largest bucket sorted in LDS
 constexpr int BK_PAIR_MAX = 128;                  // consecutive pairs per lane and round, at most
+static_assert(BK_PAIR_MAX <= 128, "a lane keeps its results in four 32-bit words");
 constexpr int BK_GROUP = 2;                       // buckets per workgroup
 constexpr int BK_OUT = 512;                       // staged output pairs per workgroup
 constexpr int BK_DIGIT = 10;                      // mix bits counted inside a bucket
@@ -1089,25 +1090,27 @@ __global__ __launch_bounds__(TH, (TH == BK_THREADS && W <= 2 && DIGIT <= 10) ? 4
         // second time for their point indices.
         constexpr uint32_t PMAX = LIST ? BK_PAIR_MAX / 2 : BK_PAIR_MAX;  // the second pass has twice the lanes
         const int cpl = (int)min(PMAX, (P + TH - 1) / TH);
-        // next pair in row-major order over the live runs
-        auto advance = [&](int& r, int& a, int& bb, int& L, int& s0) {
-            ++bb;
-            if (bb == L) {
-                ++a;
-                bb = a + 1;
-                if (a >= L - 1) {
+        // next pair in row-major order over the live runs; the walk keeps
+        // the member slots ia < ib of the pair and the end e of its run
+        // (slot s0 + L), so every slot it yields lies inside a run and
+        // below CAP; past the last run it stays on the last run
+        auto advance = [&](int& r, int& ia, int& ib, int& e) {
+            ++ib;
+            if (ib == e) {
+                ++ia;
+                ib = ia + 1;
+                if (ib >= e) {
                     ++r;
-                    a = 0;
-                    bb = 1;
                     const int rr = min(r, (int)nlive - 1);
-                    L = liveL[rr];
-                    s0 = liveS[rr];
+                    ia = liveS[rr];
+                    ib = ia + 1;
+                    e = ia + liveL[rr];
                 }
             }
         };
         for (uint32_t t0 = 0; t0 < P; t0 += TH * (uint32_t)cpl) {
             const uint32_t t = t0 + threadIdx.x * (uint32_t)cpl;
-            int r = 0, a = 0, bb = 1, L = 2, s0 = 0;
+            int r = 0, ia = 0, ib = 1, e = 2;
             int nq = 0;  // pairs of this lane
             if (t < P) {
                 int lo = 0, hi2 = (int)nlive;
@@ -1117,8 +1120,8 @@ __global__ __launch_bounds__(TH, (TH == BK_THREADS && W <= 2 && DIGIT <= 10) ? 4
                     else hi2 = mid;
                 }
                 r = lo;
-                L = liveL[r];
-                s0 = liveS[r];
+                const int L = liveL[r];
+                const int s0 = liveS[r];
                 const uint32_t u = t - liveP[r];
                 // row a of the upper triangle starts at f(a) = a (2L - a - 1) / 2;
                 // the float root is within one of the integer answer
@@ -1127,56 +1130,67 @@ __global__ __launch_bounds__(TH, (TH == BK_THREADS && W <= 2 && DIGIT <= 10) ? 4
                 aa = max(0, min(aa, L - 2));
                 if (aa < L - 2 && (uint32_t)((aa + 1) * (2 * L - aa - 2) / 2) <= u) ++aa;
                 if (aa > 0 && (uint32_t)(aa * (2 * L - aa - 1) / 2) > u) --aa;
-                a = aa;
-                bb = a + 1 + (int)(u - (uint32_t)(a * (2 * L - a - 1) / 2));
+                ia = s0 + aa;
+                ib = ia + 1 + (int)(u - (uint32_t)(aa * (2 * L - aa - 1) / 2));
+                e = s0 + L;
                 nq = (int)min((uint32_t)cpl, P - t);
             }
-            const int r_0 = r, a_0 = a, b_0 = bb, L_0 = L, s_0 = s0;
+            const int r_0 = r, ia_0 = ia, ib_0 = ib, e_0 = e;
             uint64_t ok0 = 0, ok1 = 0;  // results of pairs 0-63 and 64-127
             {
                 // the next candidate's strings are requested before the
-                // current one is tested (positions are clamped to the
-                // arrays: past a lane's last pair they are not used)
-                uint64_t sa[W], sb[W];
-                {
-                    const int pa = min(s0 + a, CAP - 1), pb = min(s0 + bb, CAP - 1);
+                // current one is tested; two candidates per trip so that
+                // the two string sets swap roles without copies. Results go
+                // to four 32-pair words, each its own unrolled loop.
+                uint64_t sa[W], sb[W], na[W], nb[W];
 #pragma unroll
-                    for (int w = 0; w < W; ++w) {
-                        sa[w] = sl[pa * W + w];
-                        sb[w] = sl[pb * W + w];
-                    }
+                for (int w = 0; w < W; ++w) {
+                    sa[w] = sl[ia * W + w];
+                    sb[w] = sl[ib * W + w];
                 }
-                for (int q = 0; q < nq; ++q) {
-                    advance(r, a, bb, L, s0);
-                    const int pa = min(s0 + a, CAP - 1), pb = min(s0 + bb, CAP - 1);
-                    uint64_t na[W], nb[W];
+                uint32_t wd[4];
 #pragma unroll
-                    for (int w = 0; w < W; ++w) {
-                        na[w] = sl[pa * W + w];
-                        nb[w] = sl[pb * W + w];
-                    }
-                    const bool ok =
-                        pair_ok_fast<W, HM, GT>(sa, sb, p, keep, hm, nhi, hi_rest, bmask, hi, dtabL, dtabG, bmL);
-                    if (q < 64) ok0 |= (uint64_t)ok << q;
-                    else ok1 |= (uint64_t)ok << (q - 64);
+                for (int qw = 0; qw < 4; ++qw) {
+                    uint32_t cur = 0;
+                    if (qw * 32 < cpl) {  // the same on every lane
+                        for (int qi = 0; qi < 32; qi += 2) {
+                            if (qw * 32 + qi >= nq) break;
+                            advance(r, ia, ib, e);
 #pragma unroll
-                    for (int w = 0; w < W; ++w) {
-                        sa[w] = na[w];
-                        sb[w] = nb[w];
+                            for (int w = 0; w < W; ++w) {
+                                na[w] = sl[ia * W + w];
+                                nb[w] = sl[ib * W + w];
+                            }
+                            cur |= (uint32_t)pair_ok_fast<W, HM, GT>(sa, sb, p, keep, hm, nhi, hi_rest, bmask, hi,
+                                                                     dtabL, dtabG, bmL)
+                                   << qi;
+                            if (qw * 32 + qi + 1 >= nq) break;
+                            advance(r, ia, ib, e);
+#pragma unroll
+                            for (int w = 0; w < W; ++w) {
+                                sa[w] = sl[ia * W + w];
+                                sb[w] = sl[ib * W + w];
+                            }
+                            cur |= (uint32_t)pair_ok_fast<W, HM, GT>(na, nb, p, keep, hm, nhi, hi_rest, bmask, hi,
+                                                                     dtabL, dtabG, bmL)
+                                   << (qi + 1);
+                        }
                     }
+                    wd[qw] = cur;
                 }
+                ok0 = (uint64_t)wd[0] | ((uint64_t)wd[1] << 32);
+                ok1 = (uint64_t)wd[2] | ((uint64_t)wd[3] << 32);
             }
             // point indices are read from LDS only for the pairs that pass
             auto bit_of = [&](int q) -> bool { return q < 64 ? ((ok0 >> q) & 1ull) : ((ok1 >> (q - 64)) & 1ull); };
             if (p.rep > 0 && (ok0 | ok1)) {
-                int r2 = r_0, a2 = a_0, b2 = b_0, L2 = L_0, s2 = s_0;
+                int r2 = r_0, ia2 = ia_0, ib2 = ib_0, e2 = e_0;
                 for (int q = 0; q < nq; ++q) {
-                    if (bit_of(q) &&
-                        !far_in_earlier<W>(p, idxB[min(s2 + a2, CAP - 1)], idxB[min(s2 + b2, CAP - 1)])) {
+                    if (bit_of(q) && !far_in_earlier<W>(p, idxB[ia2], idxB[ib2])) {
                         if (q < 64) ok0 &= ~(1ull << q);
                         else ok1 &= ~(1ull << (q - 64));
                     }
-                    advance(r2, a2, b2, L2, s2);
+                    advance(r2, ia2, ib2, e2);
                 }
             }
             // one append per lane per round: wave prefix of the counts, one
@@ -1200,12 +1214,12 @@ __global__ __launch_bounds__(TH, (TH == BK_THREADS && W <= 2 && DIGIT <= 10) ? 4
                 gbase = __shfl(gbase, 0, 64);
             }
             if (nmine) {
-                int r2 = r_0, a2 = a_0, b2 = b_0, L2 = L_0, s2 = s_0;
+                int r2 = r_0, ia2 = ia_0, ib2 = ib_0, e2 = e_0;
                 // up to the last passing pair
                 const int qend = ok1 ? 128 - __builtin_clzll(ok1) : 64 - __builtin_clzll(ok0);
                 for (int q = 0; q < qend; ++q) {
                     if (bit_of(q)) {
-                        const uint32_t iq = idxB[min(s2 + a2, CAP - 1)], jq = idxB[min(s2 + b2, CAP - 1)];
+                        const uint32_t iq = idxB[ia2], jq = idxB[ib2];
                         const uint32_t lo2 = (iq < jq ? iq : jq) - o_off;
                         const uint32_t hi3 = (iq < jq ? jq : iq) - o_off;
                         if (slot < (uint32_t)BK_OUT) {
@@ -1216,7 +1230,7 @@ __global__ __launch_bounds__(TH, (TH == BK_THREADS && W <= 2 && DIGIT <= 10) ? 4
                         }
                         ++slot;
                     }
-                    advance(r2, a2, b2, L2, s2);
+                    advance(r2, ia2, ib2, e2);
                 }
             }
             if (t0 + TH * (uint32_t)cpl < P) out.maybe_flush(BK_OUT / 2);
