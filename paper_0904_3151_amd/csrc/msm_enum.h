@@ -851,10 +851,19 @@ __global__ __launch_bounds__(TH, (TH == BK_THREADS && W <= 2 && DIGIT <= 10) ? 4
         }
     }
 
+    // one-word strings of the next bucket of the first pass, gathered while
+    // the current one is processed; pre: they are there (the same on every
+    // lane). Wider strings would take registers the pair loop needs.
+    constexpr bool PREF = !LIST && W == 1;
+    uint64_t nsreg[MAXB][W];
+    bool pre = false;
     for (int it = 0;; ++it) {
         uint32_t beg, cnt;
         uint32_t inst_id = 0;
         uint64_t cur[MAXB];
+        const bool use_pre = pre;
+        pre = false;
+        bool has_next = false;
         if (LIST) {
             const uint32_t li = blockIdx.x + (uint32_t)it * gridDim.x;
             if (li >= nlist) break;
@@ -879,7 +888,8 @@ __global__ __launch_bounds__(TH, (TH == BK_THREADS && W <= 2 && DIGIT <= 10) ? 4
             cnt = ncnt;
 #pragma unroll
             for (int b = 0; b < MAXB; ++b) cur[b] = key[b];
-            if (bk + 1 < bk1) {
+            has_next = bk + 1 < bk1;
+            if (has_next) {
                 nbeg = base[bk + 1];
                 ncnt = base[bk + 2] - nbeg;
 #pragma unroll
@@ -935,15 +945,22 @@ __global__ __launch_bounds__(TH, (TH == BK_THREADS && W <= 2 && DIGIT <= 10) ? 4
         // Batches of slots at or above m are empty for every thread; the
         // uniform tests on b * TH < m skip them with scalar branches.
         uint64_t sreg[MAXB][W];
+        if (PREF && use_pre) {
 #pragma unroll
-        for (int b = 0; b < MAXB; ++b) {
-            const int pos = threadIdx.x + b * TH;
+            for (int b = 0; b < MAXB; ++b)
 #pragma unroll
-            for (int w = 0; w < W; ++w) sreg[b][w] = 0ull;
-            if (b * TH < m && pos < m) {
-                const uint64_t idx = (uint32_t)cur[b];
+                for (int w = 0; w < W; ++w) sreg[b][w] = nsreg[b][w];
+        } else {
 #pragma unroll
-                for (int w = 0; w < W; ++w) sreg[b][w] = p.S[idx * W + w];
+            for (int b = 0; b < MAXB; ++b) {
+                const int pos = threadIdx.x + b * TH;
+#pragma unroll
+                for (int w = 0; w < W; ++w) sreg[b][w] = 0ull;
+                if (b * TH < m && pos < m) {
+                    const uint64_t idx = (uint32_t)cur[b];
+#pragma unroll
+                    for (int w = 0; w < W; ++w) sreg[b][w] = p.S[idx * W + w];
+                }
             }
         }
 
@@ -981,6 +998,22 @@ __global__ __launch_bounds__(TH, (TH == BK_THREADS && W <= 2 && DIGIT <= 10) ? 4
         }
         __syncthreads();
 
+        // the next bucket's strings are requested now (its keys arrived
+        // long ago) and arrive behind this bucket's pairs
+        if (PREF && has_next && ncnt >= 2u && ncnt <= (uint32_t)CAP) {
+#pragma unroll
+            for (int b = 0; b < MAXB; ++b) {
+                const int pos = threadIdx.x + b * TH;
+#pragma unroll
+                for (int w = 0; w < W; ++w) nsreg[b][w] = 0ull;
+                if (b * TH < (int)ncnt && pos < (int)ncnt) {
+                    const uint64_t idx = (uint32_t)key[b];
+#pragma unroll
+                    for (int w = 0; w < W; ++w) nsreg[b][w] = p.S[idx * W + w];
+                }
+            }
+            pre = true;
+        }
         // scatter run members and gather their strings
         uint32_t rfirst[MAXB], rrun[MAXB];
 #pragma unroll
