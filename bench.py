@@ -88,11 +88,14 @@ def algorithmic(kernel, w, n, C, mH, mE, W):
     Units per launch: a launch of the partition and bucket kernels covers n
     points under each of the C groupings (C(k, h) combinations of masked
     blocks, or the hierarchical groupings that replace them); k_verify covers the mH
-    candidate pairs and the n rows; k_project_f32 the n x d x ell products.
+    candidate pairs and the n rows; k_project_f32 the n x d x ell products
+    (k_project_x3 makes each of them as six BF16 products).
     """
     sb = 8 * W  # bytes of one string
     if kernel == "k_project_f32":
         return 2.0 * n * w.d * w.ell / 1e12, "TFLOP/s", "mfma"
+    if kernel == "k_project_x3":
+        return 6 * 2.0 * n * w.d * w.ell / 1e12, "TFLOP/s", "mfma_bf16"
     if kernel == "k_part_count":
         return n * C * sb / 1e9, "GB/s", "hbm"
     if kernel == "k_part_scatter":

@@ -29,10 +29,9 @@ struct Config {
     int group;   // buckets per workgroup
 };
 
-constexpr int BATCH_T = 4096;        // points per partition tile (PART_THREADS * BPART_PPT)
+constexpr int BATCH_T = BSCAT_THREADS * BPART_PPT;  // points per partition tile
 constexpr int MAX_R = 13;            // at most 8192 buckets per instance
 constexpr int PROJ_ENTRY_ROWS = 1024;  // rows per projection entry (a multiple of the tile)
-static_assert(BATCH_T <= PART_THREADS * BPART_PPT, "a partition tile must fit the scatter's registers");
 
 int bits_for(int64_t n, int target)
 {
@@ -234,7 +233,7 @@ msm_status enqueue_enumerate(msm_batch& b, int64_t* m_dev, hipStream_t s, bool t
                                s, p, ba);
             kt.reset();
             if (prof) kt.reset(new msm::KernelTimer(ctx, s, "k_bpart_scatter"));
-            hipLaunchKernelGGL((k_bpart_scatter<W>), dim3(part_grid), dim3(PART_THREADS),
+            hipLaunchKernelGGL((k_bpart_scatter<W>), dim3(part_grid), dim3(BSCAT_THREADS),
                                (size_t)BATCH_T * 8 + (size_t)b.max_nbi * 8, s, p, ba, b.max_nbi);
             kt.reset();
             if (prof) kt.reset(new msm::KernelTimer(ctx, s, "k_bucket_batch"));

@@ -51,7 +51,8 @@ constexpr int MAXK = 64;
 constexpr int PART_THREADS = 256;
 constexpr int SCAT_THREADS = 1024;  // scatter: threads, and points per thread in a chunk
 constexpr int SCAT_PPT = 16;
-constexpr int BPART_PPT = 16;       // points per thread of a batched partition tile (PART_THREADS threads)
+constexpr int BPART_PPT = 16;       // points per thread of a batched partition tile
+constexpr int BSCAT_THREADS = 256;  // threads of the batched scatter
 constexpr int SCAN_THREADS = 1024;
 constexpr int BK_THREADS = 256;
 constexpr int BK_WAVES = BK_THREADS / 64;
@@ -456,14 +457,14 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_bpart_scan(Params p, BatchArgs
     if (threadIdx.x == 0) base[nbi] = (uint32_t)(in.off + in.n);
 }
 
-// As k_part_scatter, one tile (p.T <= PART_THREADS * BPART_PPT points) at a
+// As k_part_scatter, one tile (p.T <= BSCAT_THREADS * BPART_PPT points) at a
 // time: sorted by bucket in LDS, then written in bucket runs. Dynamic LDS:
 // p.T entries, then 2 * (the largest instance bucket count) words.
 template <int W>
-__global__ __launch_bounds__(PART_THREADS) void k_bpart_scatter(Params p, BatchArgs ba, int max_nbi)
+__global__ __launch_bounds__(BSCAT_THREADS) void k_bpart_scatter(Params p, BatchArgs ba, int max_nbi)
 {
     extern __shared__ unsigned long long bscat_lds[];
-    __shared__ uint32_t wsum[PART_THREADS / 64];
+    __shared__ uint32_t wsum[BSCAT_THREADS / 64];
     int cl, t;
     if (!xcd_unit(p.units, cl, t, p.nt)) return;
     const BInst& in = ba.inst[ba.tile_inst[t]];
@@ -476,7 +477,7 @@ __global__ __launch_bounds__(PART_THREADS) void k_bpart_scatter(Params p, BatchA
     load_keep<W>(p.combos + cl, keep);
     const uint32_t* off = p.counts + (size_t)cl * ba.cnt_stride + in.cnt_off + (size_t)(t - in.tstart) * nbi;
     const uint32_t* base = p.base + (size_t)cl * (p.nb + 1) + in.bstart;
-    for (int b = threadIdx.x; b < nbi; b += PART_THREADS) {
+    for (int b = threadIdx.x; b < nbi; b += BSCAT_THREADS) {
         gb[b] = base[b] + off[b];
         lcnt[b] = 0;
     }
@@ -487,7 +488,7 @@ __global__ __launch_bounds__(PART_THREADS) void k_bpart_scatter(Params p, BatchA
     uint32_t mx[BPART_PPT], rk[BPART_PPT];
 #pragma unroll
     for (int k = 0; k < BPART_PPT; ++k) {
-        const int e = (int)threadIdx.x + k * PART_THREADS;
+        const int e = (int)threadIdx.x + k * BSCAT_THREADS;
         mx[k] = 0u;
         rk[k] = 0u;
         if (e < cnt) {
@@ -498,7 +499,7 @@ __global__ __launch_bounds__(PART_THREADS) void k_bpart_scatter(Params p, BatchA
         }
     }
     __syncthreads();
-    const int per = (nbi + PART_THREADS - 1) / PART_THREADS;
+    const int per = (nbi + BSCAT_THREADS - 1) / BSCAT_THREADS;
     const int b0 = (int)threadIdx.x * per, b1 = min(nbi, b0 + per);
     uint32_t sum = 0;
     for (int b = b0; b < b1; ++b) sum += lcnt[b];
@@ -515,14 +516,14 @@ __global__ __launch_bounds__(PART_THREADS) void k_bpart_scatter(Params p, BatchA
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < BPART_PPT; ++k) {
-        const int e = (int)threadIdx.x + k * PART_THREADS;
+        const int e = (int)threadIdx.x + k * BSCAT_THREADS;
         if (e < cnt) {
             const uint32_t b = r ? (mx[k] >> (32 - r)) : 0u;
             staged[lcnt[b] + rk[k]] = ((uint64_t)mx[k] << 32) | (uint64_t)(uint32_t)(beg + e);
         }
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < cnt; e += PART_THREADS) {
+    for (int e = threadIdx.x; e < cnt; e += BSCAT_THREADS) {
         const uint64_t v = staged[e];
         const uint32_t b = r ? ((uint32_t)(v >> 32) >> (32 - r)) : 0u;
         part[gb[b] + (uint32_t)e - lcnt[b]] = v;

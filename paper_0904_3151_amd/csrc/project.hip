@@ -12,6 +12,16 @@
 // 16-deep K chunk); workgroups are persistent, so R is staged once per
 // workgroup when it fits in 64 KB and once per row tile otherwise.
 //
+// Split-BF16 form (d <= 256 when R's three parts fit in LDS): each FP32
+// value v is written as hi + mid + lo with hi = bf16(v), mid = bf16(v - hi),
+// lo = bf16(v - hi - mid) (both differences are exact in FP32), so the three
+// parts carry v to about 24 bits. z = sum of the six products whose parts
+// are not both small (hi hi, hi mid, mid hi, mid mid, hi lo, lo hi) on
+// v_mfma_f32_16x16x32_bf16 with FP32 accumulation; the dropped terms are
+// below 2^-24 of |x_t R_tc| each, the order of FP32 rounding itself, and the
+// BF16 matrix cores do the six products in about a third of the time of
+// one FP32 product.
+//
 // K-order trick: in a 16-deep chunk lane l loads the four consecutive
 // values X[row][k0 + 4g .. k0 + 4g + 3] (g = l / 16) with one 16-byte load,
 // and MFMA j (j = 0..3) consumes component j. The MFMA's internal k index g
@@ -198,10 +208,170 @@ __global__ __launch_bounds__(PJ_THREADS) void k_project_batch(const msm::ProjIns
     }
 }
 
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int X3_THREADS = 512;
+constexpr int X3_WAVES = X3_THREADS / 64;
+constexpr int X3_CHUNKS = 8;                 // 32-deep chunks: d <= 256
+constexpr int X3_LDS_BYTES = 144 * 1024;     // the three parts of R
+constexpr int X3_MAX_NCB = 8;                // ell <= 128
+
+__device__ __forceinline__ void split3(const float (&v)[8], bf16x8& h, bf16x8& m, bf16x8& l)
+{
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const __bf16 a = (__bf16)v[i];
+        const float r1 = v[i] - (float)a;
+        const __bf16 b = (__bf16)r1;
+        const float r2 = r1 - (float)b;
+        h[i] = a;
+        m[i] = b;
+        l[i] = (__bf16)r2;
+    }
+}
+
+// Persistent workgroups of X3_WAVES waves, 16 rows per wave and all ell
+// columns (NCB blocks of 16). The parts of R sit in LDS in the B-operand
+// layout: entry (kc * NCB + cb) * 64 + l holds R[32 kc + 8 (l / 16) + i]
+// [16 cb + l % 16], i = 0..7; lane l supplies X[row l % 16][32 kc +
+// 8 (l / 16) + i], so each MFMA sums one 32-deep chunk. A wave keeps its
+// lane's slice of the row (at most 64 values) in registers and requests the
+// next tile's slice before the current tile's products.
+template <int NCB>
+__global__ __launch_bounds__(X3_THREADS) void k_project_x3(const float* __restrict__ X, int64_t n, int d,
+                                                           int64_t ldx, const float* __restrict__ R, int ell,
+                                                           uint64_t* __restrict__ S, int W, int nkc, int vec4)
+{
+    extern __shared__ __attribute__((aligned(16))) char x3_lds[];
+    const int per = nkc * NCB * 64;
+    bf16x8* Bh = reinterpret_cast<bf16x8*>(x3_lds);
+    bf16x8* Bm = Bh + per;
+    bf16x8* Bl = Bm + per;
+    for (int e = threadIdx.x; e < per; e += X3_THREADS) {
+        const int l = e & 63;
+        const int cb = (e >> 6) % NCB;
+        const int kc = (e >> 6) / NCB;
+        const int c = cb * 16 + (l & 15);
+        const int kb = kc * 32 + 8 * (l >> 4);
+        float v[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[i] = (kb + i < d && c < ell) ? R[(int64_t)(kb + i) * ell + c] : 0.0f;
+        bf16x8 h, m, lo;
+        split3(v, h, m, lo);
+        Bh[e] = h;
+        Bm[e] = m;
+        Bl[e] = lo;
+    }
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int g = lane >> 4;
+    const int r16 = lane & 15;
+    constexpr int ROWS_PER_TILE = X3_WAVES * 16;
+    const int64_t ntiles = (n + ROWS_PER_TILE - 1) / ROWS_PER_TILE;
+    auto load_rows = [&](int64_t tile, float (&xv)[X3_CHUNKS][8]) {
+        const int64_t row = tile * ROWS_PER_TILE + (int64_t)wave * 16 + r16;
+        const bool rv = tile < ntiles && row < n;
+        const float* xr = X + (rv ? row : 0) * ldx;
+#pragma unroll
+        for (int kc = 0; kc < X3_CHUNKS; ++kc) {
+            const int kb = kc * 32 + 8 * g;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) xv[kc][i] = 0.f;
+            if (kc < nkc && rv) {
+                if (vec4 && kb + 7 < d) {
+                    const floatx4 u0 = *reinterpret_cast<const floatx4*>(xr + kb);
+                    const floatx4 u1 = *reinterpret_cast<const floatx4*>(xr + kb + 4);
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        xv[kc][i] = u0[i];
+                        xv[kc][4 + i] = u1[i];
+                    }
+                } else {
+#pragma unroll
+                    for (int i = 0; i < 8; ++i)
+                        if (kb + i < d) xv[kc][i] = xr[kb + i];
+                }
+            }
+        }
+    };
+    float xn[X3_CHUNKS][8];
+    if ((int64_t)blockIdx.x < ntiles) load_rows(blockIdx.x, xn);
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        float xv[X3_CHUNKS][8];
+#pragma unroll
+        for (int kc = 0; kc < X3_CHUNKS; ++kc)
+#pragma unroll
+            for (int i = 0; i < 8; ++i) xv[kc][i] = xn[kc][i];
+        if (tile + gridDim.x < ntiles) load_rows(tile + gridDim.x, xn);
+        floatx4 acc[NCB];
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) acc[cb] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kc = 0; kc < X3_CHUNKS; ++kc) {
+            if (kc < nkc) {
+                bf16x8 ah, am, al;
+                split3(xv[kc], ah, am, al);
+#pragma unroll
+                for (int cb = 0; cb < NCB; ++cb) {
+                    const int e = (kc * NCB + cb) * 64 + lane;
+                    const bf16x8 bh = Bh[e], bm = Bm[e], bl = Bl[e];
+                    // the small terms first
+                    acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc[cb], 0, 0, 0);
+                    acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc[cb], 0, 0, 0);
+                    acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bm, acc[cb], 0, 0, 0);
+                    acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bh, acc[cb], 0, 0, 0);
+                    acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bm, acc[cb], 0, 0, 0);
+                    acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc[cb], 0, 0, 0);
+                }
+            }
+        }
+        // signs: the accumulator layout is that of the FP32 kernel
+        const int orow = lane & 15;
+        const int oword = lane >> 4;
+        uint64_t word = 0;
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) {
+            const uint64_t m0 = __ballot(acc[cb][0] > 0.0f);
+            const uint64_t m1 = __ballot(acc[cb][1] > 0.0f);
+            const uint64_t m2 = __ballot(acc[cb][2] > 0.0f);
+            const uint64_t m3 = __ballot(acc[cb][3] > 0.0f);
+            const int i = orow & 3;
+            const uint64_t mi = i == 0 ? m0 : (i == 1 ? m1 : (i == 2 ? m2 : m3));
+            const uint64_t bits = (mi >> (16 * (orow >> 2))) & 0xFFFFull;
+            if ((cb >> 2) == oword) word |= bits << (16 * (cb & 3));
+        }
+        const int64_t grow = tile * ROWS_PER_TILE + (int64_t)wave * 16 + orow;
+        if (grow < n && oword < W) S[grow * W + oword] = word;
+    }
+}
+
 template <int NCB>
 msm_status launch_project(msm_ctx* ctx, const float* X, int64_t n, int d, int64_t ldx,
                           const float* R, int ell, uint64_t* S, hipStream_t stream)
 {
+    // the split form for ell <= 128 (wider rows would not keep the X slice,
+    // the next tile's slice and the accumulators in registers)
+    const int nkc = (d + 31) / 32;
+    const size_t lds3 = (size_t)3 * nkc * NCB * 64 * sizeof(bf16x8);
+    if (NCB <= X3_MAX_NCB && nkc <= X3_CHUNKS && lds3 <= (size_t)X3_LDS_BYTES) {
+        constexpr int ROWS3 = X3_WAVES * 16;
+        const int W = (ell + 63) / 64;
+        const int vec4 = ((reinterpret_cast<uintptr_t>(X) & 15) == 0) && (ldx % 4 == 0);
+        const int64_t ntiles = (n + ROWS3 - 1) / ROWS3;
+        const int64_t grid = ntiles < (int64_t)ctx->num_cu ? ntiles : (int64_t)ctx->num_cu;
+        if (lds3 > 65536)
+            MSM_HIP(ctx, hipFuncSetAttribute(reinterpret_cast<const void*>(&k_project_x3<(NCB <= X3_MAX_NCB ? NCB : 1)>),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, X3_LDS_BYTES));
+        {
+            msm::KernelTimer kt(ctx, stream, "k_project_x3");
+            hipLaunchKernelGGL((k_project_x3<(NCB <= X3_MAX_NCB ? NCB : 1)>), dim3((unsigned)grid), dim3(X3_THREADS),
+                               lds3, stream, X, n, d, ldx, R, ell, S, W, nkc, vec4);
+        }
+        MSM_HIP(ctx, hipGetLastError());
+        return MSM_OK;
+    }
     constexpr int RB = NCB <= 4 ? 4 : (NCB <= 8 ? 2 : 1);
     constexpr int ROWS_PER_TILE = PJ_WAVES * RB * 16;
     const int W = (ell + 63) / 64;

@@ -34,7 +34,8 @@ def test_profile_only_times_one_kernel(msm, ctx):
     one_step(msm, ctx, Xd, Rd, w)
     msm.msm_profile_enable(ctx, False)
     every = msm.msm_profile_read(ctx)
-    assert {"k_project_f32", "k_bucket", "k_verify"} <= set(every)
+    assert {"k_bucket", "k_verify"} <= set(every)
+    assert {"k_project_f32", "k_project_x3"} & set(every)
     msm.msm_profile_reset(ctx)
     with pytest.raises(msm.MSMError) as e:
         msm.msm_profile_only(ctx, "x" * 48)
