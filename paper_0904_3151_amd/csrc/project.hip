@@ -215,6 +215,7 @@ constexpr int X3_WAVES = X3_THREADS / 64;
 constexpr int X3_CHUNKS = 8;                 // 32-deep chunks: d <= 256
 constexpr int X3_LDS_BYTES = 144 * 1024;     // the three parts of R
 constexpr int X3_MAX_NCB = 8;                // ell <= 128
+constexpr int X3_RB4 = 2;                    // row blocks per wave when d <= 128
 
 __device__ __forceinline__ void split3(const float (&v)[8], bf16x8& h, bf16x8& m, bf16x8& l)
 {
@@ -230,14 +231,15 @@ __device__ __forceinline__ void split3(const float (&v)[8], bf16x8& h, bf16x8& m
     }
 }
 
-// Persistent workgroups of X3_WAVES waves, 16 rows per wave and all ell
-// columns (NCB blocks of 16). The parts of R sit in LDS in the B-operand
+// Persistent workgroups of X3_WAVES waves, 16 * RB rows per wave and all
+// ell columns (NCB blocks of 16). The parts of R sit in LDS in the B-operand
 // layout: entry (kc * NCB + cb) * 64 + l holds R[32 kc + 8 (l / 16) + i]
 // [16 cb + l % 16], i = 0..7; lane l supplies X[row l % 16][32 kc +
-// 8 (l / 16) + i], so each MFMA sums one 32-deep chunk. A wave keeps its
-// lane's slice of the row (at most 64 values) in registers and requests the
-// next tile's slice before the current tile's products.
-template <int NCB>
+// 8 (l / 16) + i], so each MFMA sums one 32-deep chunk, and each B read
+// serves the wave's RB row blocks. A wave keeps its lane's slices of the
+// rows (KC chunks of 8 values) in registers and requests the next tile's
+// slices before the current tile's products.
+template <int NCB, int KC, int RB>
 __global__ __launch_bounds__(X3_THREADS) void k_project_x3(const float* __restrict__ X, int64_t n, int d,
                                                            int64_t ldx, const float* __restrict__ R, int ell,
                                                            uint64_t* __restrict__ S, int W, int nkc, int vec4)
@@ -268,83 +270,121 @@ __global__ __launch_bounds__(X3_THREADS) void k_project_x3(const float* __restri
     const int wave = threadIdx.x >> 6;
     const int g = lane >> 4;
     const int r16 = lane & 15;
-    constexpr int ROWS_PER_TILE = X3_WAVES * 16;
+    constexpr int ROWS_PER_TILE = X3_WAVES * 16 * RB;
     const int64_t ntiles = (n + ROWS_PER_TILE - 1) / ROWS_PER_TILE;
-    auto load_rows = [&](int64_t tile, float (&xv)[X3_CHUNKS][8]) {
-        const int64_t row = tile * ROWS_PER_TILE + (int64_t)wave * 16 + r16;
-        const bool rv = tile < ntiles && row < n;
-        const float* xr = X + (rv ? row : 0) * ldx;
+    auto load_rows = [&](int64_t tile, float (&xv)[RB][KC][8]) {
 #pragma unroll
-        for (int kc = 0; kc < X3_CHUNKS; ++kc) {
-            const int kb = kc * 32 + 8 * g;
+        for (int rb = 0; rb < RB; ++rb) {
+            const int64_t row = tile * ROWS_PER_TILE + ((int64_t)wave * RB + rb) * 16 + r16;
+            const bool rv = tile < ntiles && row < n;
+            const float* xr = X + (rv ? row : 0) * ldx;
 #pragma unroll
-            for (int i = 0; i < 8; ++i) xv[kc][i] = 0.f;
-            if (kc < nkc && rv) {
-                if (vec4 && kb + 7 < d) {
-                    const floatx4 u0 = *reinterpret_cast<const floatx4*>(xr + kb);
-                    const floatx4 u1 = *reinterpret_cast<const floatx4*>(xr + kb + 4);
+            for (int kc = 0; kc < KC; ++kc) {
+                const int kb = kc * 32 + 8 * g;
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        xv[kc][i] = u0[i];
-                        xv[kc][4 + i] = u1[i];
+                for (int i = 0; i < 8; ++i) xv[rb][kc][i] = 0.f;
+                if (kc < nkc && rv) {
+                    if (vec4 && kb + 7 < d) {
+                        const floatx4 u0 = *reinterpret_cast<const floatx4*>(xr + kb);
+                        const floatx4 u1 = *reinterpret_cast<const floatx4*>(xr + kb + 4);
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            xv[rb][kc][i] = u0[i];
+                            xv[rb][kc][4 + i] = u1[i];
+                        }
+                    } else {
+#pragma unroll
+                        for (int i = 0; i < 8; ++i)
+                            if (kb + i < d) xv[rb][kc][i] = xr[kb + i];
                     }
-                } else {
-#pragma unroll
-                    for (int i = 0; i < 8; ++i)
-                        if (kb + i < d) xv[kc][i] = xr[kb + i];
                 }
             }
         }
     };
-    float xn[X3_CHUNKS][8];
+    float xn[RB][KC][8];
     if ((int64_t)blockIdx.x < ntiles) load_rows(blockIdx.x, xn);
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        float xv[X3_CHUNKS][8];
+        float xv[RB][KC][8];
 #pragma unroll
-        for (int kc = 0; kc < X3_CHUNKS; ++kc)
+        for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-            for (int i = 0; i < 8; ++i) xv[kc][i] = xn[kc][i];
+            for (int kc = 0; kc < KC; ++kc)
+#pragma unroll
+                for (int i = 0; i < 8; ++i) xv[rb][kc][i] = xn[rb][kc][i];
         if (tile + gridDim.x < ntiles) load_rows(tile + gridDim.x, xn);
-        floatx4 acc[NCB];
+        floatx4 acc[RB][NCB];
 #pragma unroll
-        for (int cb = 0; cb < NCB; ++cb) acc[cb] = floatx4{0.f, 0.f, 0.f, 0.f};
+        for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-        for (int kc = 0; kc < X3_CHUNKS; ++kc) {
+            for (int cb = 0; cb < NCB; ++cb) acc[rb][cb] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kc = 0; kc < KC; ++kc) {
             if (kc < nkc) {
-                bf16x8 ah, am, al;
-                split3(xv[kc], ah, am, al);
+                bf16x8 ah[RB], am[RB], al[RB];
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb) split3(xv[rb][kc], ah[rb], am[rb], al[rb]);
 #pragma unroll
                 for (int cb = 0; cb < NCB; ++cb) {
                     const int e = (kc * NCB + cb) * 64 + lane;
                     const bf16x8 bh = Bh[e], bm = Bm[e], bl = Bl[e];
-                    // the small terms first
-                    acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc[cb], 0, 0, 0);
-                    acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc[cb], 0, 0, 0);
-                    acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bm, acc[cb], 0, 0, 0);
-                    acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bh, acc[cb], 0, 0, 0);
-                    acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bm, acc[cb], 0, 0, 0);
-                    acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc[cb], 0, 0, 0);
+#pragma unroll
+                    for (int rb = 0; rb < RB; ++rb) {
+                        // the small terms first
+                        floatx4 a = acc[rb][cb];
+                        a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[rb], bh, a, 0, 0, 0);
+                        a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[rb], bl, a, 0, 0, 0);
+                        a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am[rb], bm, a, 0, 0, 0);
+                        a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am[rb], bh, a, 0, 0, 0);
+                        a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[rb], bm, a, 0, 0, 0);
+                        acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[rb], bh, a, 0, 0, 0);
+                    }
                 }
             }
         }
         // signs: the accumulator layout is that of the FP32 kernel
         const int orow = lane & 15;
         const int oword = lane >> 4;
-        uint64_t word = 0;
 #pragma unroll
-        for (int cb = 0; cb < NCB; ++cb) {
-            const uint64_t m0 = __ballot(acc[cb][0] > 0.0f);
-            const uint64_t m1 = __ballot(acc[cb][1] > 0.0f);
-            const uint64_t m2 = __ballot(acc[cb][2] > 0.0f);
-            const uint64_t m3 = __ballot(acc[cb][3] > 0.0f);
-            const int i = orow & 3;
-            const uint64_t mi = i == 0 ? m0 : (i == 1 ? m1 : (i == 2 ? m2 : m3));
-            const uint64_t bits = (mi >> (16 * (orow >> 2))) & 0xFFFFull;
-            if ((cb >> 2) == oword) word |= bits << (16 * (cb & 3));
+        for (int rb = 0; rb < RB; ++rb) {
+            uint64_t word = 0;
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) {
+                const uint64_t m0 = __ballot(acc[rb][cb][0] > 0.0f);
+                const uint64_t m1 = __ballot(acc[rb][cb][1] > 0.0f);
+                const uint64_t m2 = __ballot(acc[rb][cb][2] > 0.0f);
+                const uint64_t m3 = __ballot(acc[rb][cb][3] > 0.0f);
+                const int i = orow & 3;
+                const uint64_t mi = i == 0 ? m0 : (i == 1 ? m1 : (i == 2 ? m2 : m3));
+                const uint64_t bits = (mi >> (16 * (orow >> 2))) & 0xFFFFull;
+                if ((cb >> 2) == oword) word |= bits << (16 * (cb & 3));
+            }
+            const int64_t grow = tile * ROWS_PER_TILE + ((int64_t)wave * RB + rb) * 16 + orow;
+            if (grow < n && oword < W) S[grow * W + oword] = word;
         }
-        const int64_t grow = tile * ROWS_PER_TILE + (int64_t)wave * 16 + orow;
-        if (grow < n && oword < W) S[grow * W + oword] = word;
     }
+}
+
+// Launches k_project_x3 with the chunk count that covers d and the row
+// blocks per wave that fit the registers.
+template <int NCB, int KC, int RB>
+msm_status launch_x3(msm_ctx* ctx, const float* X, int64_t n, int d, int64_t ldx, const float* R, int ell,
+                     uint64_t* S, int nkc, size_t lds3, hipStream_t stream)
+{
+    constexpr int ROWS3 = X3_WAVES * 16 * RB;
+    const int W = (ell + 63) / 64;
+    const int vec4 = ((reinterpret_cast<uintptr_t>(X) & 15) == 0) && (ldx % 4 == 0);
+    const int64_t ntiles = (n + ROWS3 - 1) / ROWS3;
+    const int64_t grid = ntiles < (int64_t)ctx->num_cu ? ntiles : (int64_t)ctx->num_cu;
+    if (lds3 > 65536)
+        MSM_HIP(ctx, hipFuncSetAttribute(reinterpret_cast<const void*>(&k_project_x3<NCB, KC, RB>),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, X3_LDS_BYTES));
+    {
+        msm::KernelTimer kt(ctx, stream, "k_project_x3");
+        hipLaunchKernelGGL((k_project_x3<NCB, KC, RB>), dim3((unsigned)grid), dim3(X3_THREADS), lds3, stream, X, n,
+                           d, ldx, R, ell, S, W, nkc, vec4);
+    }
+    MSM_HIP(ctx, hipGetLastError());
+    return MSM_OK;
 }
 
 template <int NCB>
@@ -355,22 +395,11 @@ msm_status launch_project(msm_ctx* ctx, const float* X, int64_t n, int d, int64_
     // the next tile's slice and the accumulators in registers)
     const int nkc = (d + 31) / 32;
     const size_t lds3 = (size_t)3 * nkc * NCB * 64 * sizeof(bf16x8);
-    if (NCB <= X3_MAX_NCB && nkc <= X3_CHUNKS && lds3 <= (size_t)X3_LDS_BYTES) {
-        constexpr int ROWS3 = X3_WAVES * 16;
-        const int W = (ell + 63) / 64;
-        const int vec4 = ((reinterpret_cast<uintptr_t>(X) & 15) == 0) && (ldx % 4 == 0);
-        const int64_t ntiles = (n + ROWS3 - 1) / ROWS3;
-        const int64_t grid = ntiles < (int64_t)ctx->num_cu ? ntiles : (int64_t)ctx->num_cu;
-        if (lds3 > 65536)
-            MSM_HIP(ctx, hipFuncSetAttribute(reinterpret_cast<const void*>(&k_project_x3<(NCB <= X3_MAX_NCB ? NCB : 1)>),
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, X3_LDS_BYTES));
-        {
-            msm::KernelTimer kt(ctx, stream, "k_project_x3");
-            hipLaunchKernelGGL((k_project_x3<(NCB <= X3_MAX_NCB ? NCB : 1)>), dim3((unsigned)grid), dim3(X3_THREADS),
-                               lds3, stream, X, n, d, ldx, R, ell, S, W, nkc, vec4);
-        }
-        MSM_HIP(ctx, hipGetLastError());
-        return MSM_OK;
+    if constexpr (NCB <= X3_MAX_NCB) {
+        if (nkc <= 4 && lds3 <= (size_t)X3_LDS_BYTES)
+            return launch_x3<NCB, 4, X3_RB4>(ctx, X, n, d, ldx, R, ell, S, nkc, lds3, stream);
+        if (nkc <= X3_CHUNKS && lds3 <= (size_t)X3_LDS_BYTES)
+            return launch_x3<NCB, X3_CHUNKS, 1>(ctx, X, n, d, ldx, R, ell, S, nkc, lds3, stream);
     }
     constexpr int RB = NCB <= 4 ? 4 : (NCB <= 8 ? 2 : 1);
     constexpr int ROWS_PER_TILE = PJ_WAVES * RB * 16;
