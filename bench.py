@@ -681,7 +681,9 @@ def main():
         "data": f"synthetic Gaussian mixture, sigma_mode={args.sigma_mode}",
         "config": {"workload": w.name, "n": n, "d": w.d, "ell": w.ell, "k": w.k, "h": w.h, "eps": w.eps,
                    "metric": w.metric, "groupings": res["combinations"], "hier_j": res["hier_j"],
-                   "sigma_mode": args.sigma_mode},
+                   "sigma_mode": args.sigma_mode,
+                   "projection_arith": ("fp32 as three bf16 parts, six products, fp32 accumulation"
+                                        if w.ell <= 128 and w.d <= 256 else "fp32 products")},
         "edges_per_s": {"hamming_pairs_per_s_enumerate": c["hamming_pairs_per_s_enumerate"],
                         "eps_pairs_per_s_total": c["eps_pairs_per_s_total"]},
         "counts": {"hamming_pairs": res["hamming_pairs"], "eps_pairs": res["eps_pairs"]},

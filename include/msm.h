@@ -84,7 +84,10 @@ const char* msm_last_error(const msm_ctx* ctx);
 
 /* Random-projection LSH, Section 3.2, eq. (3):
  *   z_ic = sum_t X[i,t] * R[t,c],   bit c of S_i = 1 iff z_ic > 0, else 0.
- * FP32 multiply-add with FP32 accumulation on the matrix cores.
+ * FP32 accumulation on the matrix cores. For ell <= 128 and d <= 256 each
+ * FP32 input is split into three BF16 parts (hi, mid, lo) and z sums the six
+ * products whose parts are not both small, which carries the products to
+ * about FP32 precision; other shapes use FP32 products.
  *   X    DEVICE float[n rows, ldx stride]   input vectors
  *   R    DEVICE float[d * ell]              projection matrix, row-major
  *   S    DEVICE uint64[n * W]               output strings (fully written)
