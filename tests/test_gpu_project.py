@@ -53,6 +53,9 @@ def test_project_tiny_workload(msm, ctx):
     (17, 16, 64, 0, 0),
     (1, 5, 17, 0, 0),
     (129, 128, 128, 4, 0),
+    (400, 200, 96, 0, 0),      # split form over eight 32-deep chunks
+    (250, 250, 64, 2, 0),      # the same with strided rows
+    (300, 256, 128, 0, 0),     # split parts of R above LDS: FP32 products
 ])
 def test_project_shapes(msm, ctx, n, d, ell, pad, off):
     X, _ = I.gaussian_mixture(n, d, max(1, n // 20), 0.2, seed=n + d, sigma_mode="coord")
