@@ -113,7 +113,7 @@ def algorithmic(kernel, w, n, C, mH, mE, W):
 
 def missing_edge_ratio(msm, ctx, w, Xd, hamming, verified, sub=None):
     """|E* minus E_eps| / |E*| on a seeded subsample (Section 4.2), where E* is
-    the exhaustive epsilon graph of the subsample (the judge) and E_eps the
+    the exhaustive epsilon graph of the subsample (the exhaustive reference) and E_eps the
     verified pairs with both ends in it. Every MSM decision is per pair, so
     restricting to the subsample is exact."""
     import torch
@@ -124,7 +124,7 @@ def missing_edge_ratio(msm, ctx, w, Xd, hamming, verified, sub=None):
     t0 = time.perf_counter()
     star, mstar = msm.bruteforce_eps(ctx, Xd[sub].contiguous(), w.metric, w.eps, cap_hint=1 << 22)
     torch.cuda.synchronize()
-    t_judge = time.perf_counter() - t0
+    t_ref = time.perf_counter() - t0
     n = Xd.shape[0]
     insub = torch.zeros(n, dtype=torch.bool, device=Xd.device)
     insub[sub] = True
@@ -142,7 +142,7 @@ def missing_edge_ratio(msm, ctx, w, Xd, hamming, verified, sub=None):
     false_pos = int((~torch.isin(ham, star_codes)).sum()) if ham.numel() else 0
     return {"subsample": int(sub.numel()), "true_pairs": int(mstar), "missed": missed,
             "ratio": (missed / mstar) if mstar else None,
-            "type1_candidates": false_pos, "judge_s": round(t_judge, 3),
+            "type1_candidates": false_pos, "reference_s": round(t_ref, 3),
             "note": None if mstar else "no pair of the subsample is within eps"}
 
 
@@ -254,16 +254,16 @@ def run_precision(args):
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
            "data": "synthetic sparse lognormal rows",
            "config": {"workload": w.name, "n": n, "d": w.d, "ell": w.ell, "k": w.k, "h": w.h, "eps": w.eps,
-                      "metric": w.metric, "tau": tau, "judge_subsample": int(sub.numel()),
-                      "judge_true_pairs": int(mstar)},
+                      "metric": w.metric, "tau": tau, "reference_subsample": int(sub.numel()),
+                      "reference_true_pairs": int(mstar)},
            "per_dtype": per}
     print(json.dumps(out), flush=True)
     ctx.close()
 
 
-def run_mixture(msm, ctx, w, X, Xd, project, steps, warmup, judge_sub=None):
+def run_mixture(msm, ctx, w, X, Xd, project, steps, warmup, ref_sub=None):
     """Time `steps` whole steps (project, enumerate, verify) over a mixture
-    workload already on the device, then judge the missing-edge ratio.
+    workload already on the device, then measure the missing-edge ratio.
     `project(S)` writes the strings. Returns a dict of results."""
     import torch
 
@@ -319,7 +319,7 @@ def run_mixture(msm, ctx, w, X, Xd, project, steps, warmup, judge_sub=None):
                        "timed_region": name == dom}
     t_enum = sum(v["ms_per_step"] for k, v in phase.items()
                  if k in ("k_part_count", "k_part_scan", "k_part_scatter", "k_bucket", "k_big"))
-    missing = missing_edge_ratio(msm, ctx, w, Xd, pairs[:mH], verified[:mE], sub=judge_sub)
+    missing = missing_edge_ratio(msm, ctx, w, Xd, pairs[:mH], verified[:mE], sub=ref_sub)
     res = {"ms_per_step": ms_step, "points_per_s": n / (ms_step / 1e3), "combinations": C, "hier_j": jblk,
            "hamming_pairs": int(mH), "eps_pairs": int(mE), "phase": phase,
            "hamming_pairs_per_s_enumerate": (mH / (t_enum / 1e3)) if t_enum else None,
@@ -357,9 +357,9 @@ def compact(res):
 def run_learned(args):
     """The learned-projection form: 2M mixture points (cluster radius reading
     of sigma), a 128-512-128 network trained on the GPU on epsilon-pairs and
-    non-pairs mined by the exhaustive judge from a 100k-point sample, then
+    non-pairs mined by the exhaustive search from a 100k-point sample, then
     whole steps with learned and with random strings at equal ell, each
-    judged on a 50k subsample disjoint from the training sample."""
+    measured on a 50k subsample disjoint from the training sample."""
     import numpy as np
     import torch
 
@@ -377,7 +377,7 @@ def run_learned(args):
     ctx = msm.Context(0)
     train_idx = I.subsample_indices(n, 100_000, w.seed_sub + 7)
     held = np.setdiff1d(np.arange(n, dtype=np.int64), train_idx)
-    judge_sub = torch.from_numpy(held[I.subsample_indices(held.size, w.subsample, w.seed_sub)]).to(dev)
+    ref_sub = torch.from_numpy(held[I.subsample_indices(held.size, w.subsample, w.seed_sub)]).to(dev)
     Xt = Xd[torch.from_numpy(train_idx).to(dev)].contiguous()
     t0 = time.perf_counter()
     tp, tl, stats = L.mine_pairs(ctx, Xt, w.eps, n_pos=200_000, n_neg=200_000, seed=w.seed_sub + 8)
@@ -395,10 +395,10 @@ def run_learned(args):
         f"loss {losses[0]:.3f} -> {np.mean(losses[-20:]):.3f}")
 
     learned = run_mixture(msm, ctx, w, X, Xd, lambda S: msm.msm_project_mlp(ctx, Xd, params, cfg.hid, w.ell, S),
-                          args.steps, args.warmup, judge_sub)
+                          args.steps, args.warmup, ref_sub)
     log(f"learned: {compact(learned)}")
     rand = run_mixture(msm, ctx, w, X, Xd, lambda S: msm.msm_project(ctx, Xd, Rd, S), args.steps, args.warmup,
-                       judge_sub)
+                       ref_sub)
     log(f"random: {compact(rand)}")
     flops = 2.0 * n * (w.d * cfg.hid + cfg.hid * w.ell)
     ph = learned["phase"].get("k_mlp_fused")
@@ -414,7 +414,7 @@ def run_learned(args):
            "data": "synthetic Gaussian mixture, sigma_mode=radius",
            "config": {"workload": w.name, "n": n, "d": w.d, "ell": w.ell, "k": w.k, "h": w.h, "eps": w.eps,
                       "metric": w.metric, "hidden": cfg.hid, "train_sample": int(train_idx.size),
-                      "judge_subsample": int(judge_sub.numel())},
+                      "reference_subsample": int(ref_sub.numel())},
            "training": {"mining": stats, "mining_s": round(t_mine, 2), "steps": nsteps - 1,
                         "train_s": round(t_train, 2), "loss_first": losses[0],
                         "loss_last20": float(np.mean(losses[-20:])), "config": vars(cfg)},

@@ -199,7 +199,7 @@ msm_status msm_verify(msm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_
                       uint32_t* out, int64_t cap, int64_t* m_out, void* stream);
 
 /* Exhaustive epsilon-neighbour enumeration, Definition 1.1: every (i, j),
- * i < j, with Delta(x_i, x_j) <= eps. This is the judge for the
+ * i < j, with Delta(x_i, x_j) <= eps. This is the exhaustive reference for the
  * missing-edge ratio of Section 4.2 (|F2| / |E*| on a subsample), not part
  * of the MSM path. FP32 Gram-matrix screening on the matrix cores with a
  * rounding band, then an FP64 evaluation of each screened pair from the

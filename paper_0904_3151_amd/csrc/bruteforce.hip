@@ -1,5 +1,5 @@
 // Exhaustive epsilon-neighbour enumeration (Definition 1.1), used as the
-// judge of the missing-edge ratio (Section 4.2) on a subsample.
+// exhaustive reference of the missing-edge ratio (Section 4.2) on a subsample.
 //
 // The O(n^2) distances come from a Gram matrix on the FP32 matrix cores:
 // ||x_i - x_j||^2 = |x_i|^2 + |x_j|^2 - 2 x_i.x_j (cosine: 1 - x_i.x_j /

@@ -1,12 +1,12 @@
 """Learned projection around the library's kernels: mining labelled pairs
-with the exhaustive judge, training with msm_mlp_train, and saving or
+with the exhaustive search, training with msm_mlp_train, and saving or
 loading the trained parameters.
 
 The network (two layers, GELU, tanh output; the sign of the output layer's
 pre-activation is the bit) replaces the random projection R of eq. (3), the
 non-random hashing the paper names in Section 6. Training pairs come from
 the exact method on a sample: epsilon-pairs found by msm_bruteforce_eps
-(label 1), and pairs beyond epsilon (label 0) drawn half from the judge's
+(label 1), and pairs beyond epsilon (label 0) drawn half from the exhaustive search's
 pairs within 2 eps (hard negatives) and half uniformly. Host code here only
 draws indices and orders the pair list; all arithmetic runs in libmsm.
 """

@@ -1,5 +1,5 @@
 """Parity of msm_bruteforce_eps (Definition 1.1 by exhaustive search, the
-judge of the missing-edge ratio) with the oracle's exhaustive search. Both
+exhaustive reference of the missing-edge ratio) with the oracle's exhaustive search. Both
 decide in FP64 from the same FP32 inputs, so the sets agree except for pairs
 within 1e-9 (relative) of the threshold."""
 import numpy as np
@@ -62,7 +62,7 @@ def test_bruteforce_cosine_sparse(msm, ctx):
 
 
 def test_bruteforce_equals_hamming_free_verify(msm, ctx):
-    # the judge and verify over all pairs agree on a random cloud
+    # the exhaustive reference and verify over all pairs agree on a random cloud
     X, _ = I.workload_inputs(I.TINY, sigma_mode="radius", n=1500)
     Xd = torch.from_numpy(X).cuda()
     out, m = msm.bruteforce_eps(ctx, Xd, "euclidean", 0.4)
