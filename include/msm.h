@@ -144,6 +144,25 @@ msm_status msm_enumerate_pairs(msm_ctx* ctx, const uint64_t* S, int64_t n, int32
                                int32_t k, int32_t h, uint32_t* pairs, int64_t cap,
                                int64_t* m_out, void* stream);
 
+/* msm_enumerate_pairs for callers that cannot allocate memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, same pair set, same errors, but the work memory is a fixed
+ * 64 MiB device buffer that the library holds per device (a static array,
+ * kept until the process ends) instead of the context's growing scratch,
+ * and the host tables go up through a pinned buffer the context allocated
+ * when it was created. The call makes no device or host allocation.
+ * Additional errors: MSM_E_UNSUPPORTED when the work memory for n strings
+ * does not fit in the buffer (n above about 6 million; the message gives
+ * the bytes needed) or the tables of the C(k, h) combinations exceed 2 MiB
+ * (C(k, h) above about 10000); nothing is computed then and *m_out is 0.
+ * All calls on one device share that device's buffer, and a call leaves its
+ * contents behind (the next call clears what it needs): calls that overlap
+ * on one device, from several host threads, streams or contexts, race and
+ * give undefined results. Synchronises `stream` before returning. */
+msm_status msm_enumerate_pairs_noalloc(msm_ctx* ctx, const uint64_t* S, int64_t n, int32_t ell,
+                                       int32_t k, int32_t h, uint32_t* pairs, int64_t cap,
+                                       int64_t* m_out, void* stream);
+
 /* How msm_enumerate_pairs may group n strings of ell bits for (k, h): the
  * number of groupings (partition passes) it makes and, when it groups on
  * j < k - h blocks (hierarchically: one grouping on a set A of j blocks

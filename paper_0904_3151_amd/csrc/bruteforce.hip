@@ -206,7 +206,7 @@ extern "C" msm_status msm_bruteforce_eps(msm_ctx* ctx, const float* X, int64_t n
     cv.take<unsigned long long>(2);
     cv.take<float>((size_t)n);
     void* scr = nullptr;
-    st = msm::scratch(ctx, cv.off, s, &scr);
+    st = msm::ctx_scratch(ctx, cv.off, s, &scr);
     if (st != MSM_OK) return st;
     msm::Carver c2;
     c2.base = static_cast<char*>(scr);

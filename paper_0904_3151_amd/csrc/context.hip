@@ -2,10 +2,39 @@
 #include "msm_internal.h"
 
 #include <cstring>
+#include <mutex>
+
+// Work memory of msm_enumerate_pairs_noalloc, for callers that cannot
+// allocate device memory. Every device the library runs on holds its own
+// copy until the process ends. In host code this name is only a handle for
+// hipGetSymbolAddress: kernels are given the device address it returns
+// (kept per device in g_noalloc_ptr), never the name itself.
+static __device__ __align__(256) unsigned char scratch[msm::NOALLOC_SCRATCH_BYTES];
 
 namespace {
 thread_local std::string g_create_err;
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// The device address of `scratch` on `device`, which must be current:
+// resolved on the first call for that device, then reused.
+hipError_t noalloc_address(int device, void** out)
+{
+    *out = nullptr;
+    if (device < 0 || device >= NOALLOC_MAX_DEVICES) return hipSuccess;
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    if (!g_noalloc_ptr[device]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_noalloc_ptr[device] = ptr;
+    }
+    *out = g_noalloc_ptr[device];
+    return hipSuccess;
 }
+}  // namespace
 
 namespace msm {
 
@@ -36,7 +65,7 @@ msm_status use_device(msm_ctx* ctx)
     return MSM_OK;
 }
 
-msm_status scratch(msm_ctx* ctx, size_t bytes, hipStream_t stream, void** out)
+msm_status ctx_scratch(msm_ctx* ctx, size_t bytes, hipStream_t stream, void** out)
 {
     bytes = align_up(bytes < 256 ? 256 : bytes, 256);
     if (bytes > ctx->scratch_bytes) {
@@ -151,6 +180,20 @@ msm_status msm_create(int32_t device, msm_ctx** out)
         delete ctx;
         return msm::hip_fail(nullptr, e, "hipHostMalloc");
     }
+    e = hipHostMalloc((void**)&ctx->host_stage, msm::NOALLOC_STAGE_BYTES, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        (void)hipHostFree(ctx->host_words);
+        delete ctx;
+        return msm::hip_fail(nullptr, e, "hipHostMalloc");
+    }
+    // the no-allocation scratch of this device, with the device current
+    e = noalloc_address(device, &ctx->noalloc_scratch);
+    if (e != hipSuccess) {
+        (void)hipHostFree(ctx->host_stage);
+        (void)hipHostFree(ctx->host_words);
+        delete ctx;
+        return msm::hip_fail(nullptr, e, "hipGetSymbolAddress(scratch)");
+    }
     *out = ctx;
     return MSM_OK;
 }
@@ -168,6 +211,7 @@ void msm_destroy(msm_ctx* ctx)
     for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
     if (ctx->scratch) (void)hipFree(ctx->scratch);
     if (ctx->host_words) (void)hipHostFree(ctx->host_words);
+    if (ctx->host_stage) (void)hipHostFree(ctx->host_stage);
     if (cur >= 0 && cur != ctx->device) (void)hipSetDevice(cur);
     delete ctx;
 }

@@ -46,9 +46,64 @@ void launch_bucket(int hm, bool large, dim3 grid, hipStream_t stream, const Para
     else launch_bucket_hier<W, true>(hm, large, grid, stream, p);
 }
 
+// Device memory of one enumeration, carved from one buffer: the host tables
+// first (in one piece, so that one copy uploads them), then the counters,
+// the probe's histograms and the partition arrays of Cg groupings.
+struct EnumMem {
+    Combo* combos_std;
+    Combo* combos_h;
+    Combo* full;
+    uint64_t* fam;
+    uint32_t* dtab;
+    uint64_t* bm;
+    size_t table_bytes;
+    unsigned long long* counter;
+    uint32_t* ovfc;
+    uint64_t* part;
+    uint32_t* counts;
+    uint32_t* probe;
+    unsigned long long* work;
+    uint32_t* base;
+    Ovf* ovf;
+    Ovf* ovf2;
+    uint64_t* tile0;
+};
+
+// Lays EnumMem out from c.base (NULL: only sizes, in c.off).
+inline EnumMem carve_enum(msm::Carver& c, int Cstd, int Ch, size_t nfam, size_t ndtab, int k, bool probe,
+                          int Cg, int64_t n, int nt, int nb)
+{
+    EnumMem m{};
+    m.combos_std = c.take<Combo>((size_t)Cstd);
+    m.combos_h = c.take<Combo>((size_t)std::max(1, Ch));
+    m.full = c.take<Combo>(1);
+    m.fam = c.take<uint64_t>(std::max<size_t>(1, nfam));
+    m.dtab = c.take<uint32_t>(std::max<size_t>(1, ndtab));
+    m.bm = c.take<uint64_t>((size_t)k * MAXW);
+    m.table_bytes = c.off;
+    m.counter = c.take<unsigned long long>(4);
+    m.ovfc = c.take<uint32_t>(4);
+    m.part = c.take<uint64_t>((size_t)Cg * n);
+    m.counts = c.take<uint32_t>((size_t)Cg * nt * nb);
+    m.probe = c.take<uint32_t>(probe ? (size_t)(PROBE_HIER + PROBE_STD + 1) * PROBE_BINS : 1);
+    m.work = c.take<unsigned long long>(1);
+    m.base = c.take<uint32_t>((size_t)Cg * (nb + 1));
+    m.ovf = c.take<Ovf>((size_t)Cg * nb);
+    m.ovf2 = c.take<Ovf>((size_t)Cg * nb);
+    m.tile0 = c.take<uint64_t>((size_t)Cg * nb + 1);
+    return m;
+}
+
+// ext == NULL: the work memory is the context's scratch, grown as needed and
+// at most about 3 GB of partition arrays per launch group. Otherwise it is
+// the ext_bytes at ext (device memory the call does not own) and the host
+// tables go up through the context's pinned staging buffer, so the call
+// allocates nothing; it fails with MSM_E_UNSUPPORTED when one grouping's
+// arrays do not fit.
 template <int W>
 msm_status run_enumerate(msm_ctx* ctx, const uint64_t* S, int64_t n, int ell, int Q, int k, int h,
-                         uint32_t* pairs, int64_t cap, int64_t* m_out, hipStream_t stream)
+                         uint32_t* pairs, int64_t cap, int64_t* m_out, hipStream_t stream, void* ext,
+                         size_t ext_bytes)
 {
     std::vector<uint64_t> bm;
     uint64_t valid[MAXW];
@@ -79,61 +134,71 @@ msm_status run_enumerate(msm_ctx* ctx, const uint64_t* S, int64_t n, int ell, in
     while (sch > SCAT_THREADS && (size_t)sch * 8 + (size_t)nb * 8 > (size_t)150 * 1024) sch /= 2;
     const size_t scat_lds = (size_t)sch * 8 + (size_t)nb * 8;
 
-    // Combinations per launch group, bounded by scratch size.
+    // Combinations per launch group, bounded by the memory for them.
     const size_t per_combo = msm::align_up((size_t)n * 8, 256) + msm::align_up((size_t)nt * nb * 4, 256) +
-                             msm::align_up((size_t)(nb + 1) * 4, 256) + 2 * msm::align_up((size_t)nb * sizeof(Ovf), 256);
+                             msm::align_up((size_t)(nb + 1) * 4, 256) + 3 * msm::align_up((size_t)nb * sizeof(Ovf), 256);
+    auto bytes_for = [&](int cg) {
+        msm::Carver c;
+        carve_enum(c, Cstd, Ch, fam.size(), dtab.size(), k, hier_cand, cg, n, nt, nb);
+        return c.off;
+    };
     const size_t budget = (size_t)3 << 30;
     int Cg = (int)std::max<size_t>(1, std::min<size_t>((size_t)Cmax, budget / per_combo));
     Cg = std::min(Cg, 65535);
+    if (ext) {
+        const size_t fixed = bytes_for(0);
+        if (fixed >= ext_bytes || bytes_for(1) > ext_bytes)
+            return msm::fail(ctx, MSM_E_UNSUPPORTED,
+                             "msm_enumerate_pairs_noalloc: n=%lld strings need %zu bytes of work memory, above "
+                             "the %zu of the no-allocation buffer",
+                             (long long)n, bytes_for(1), ext_bytes);
+        Cg = (int)std::min<size_t>((size_t)Cg, (ext_bytes - fixed) / per_combo);
+        Cg = std::max(Cg, 1);
+        while (Cg > 1 && bytes_for(Cg) > ext_bytes) --Cg;
+    }
 
-    // the host tables come first in scratch, in one piece, so that one copy
-    // uploads them
-    msm::Carver cv;
-    cv.take<Combo>((size_t)Cstd);
-    cv.take<Combo>((size_t)std::max(1, Ch));
-    cv.take<Combo>(1);
-    cv.take<uint64_t>(std::max<size_t>(1, fam.size()));
-    cv.take<uint32_t>(std::max<size_t>(1, dtab.size()));
-    cv.take<uint64_t>((size_t)k * MAXW);
-    const size_t table_bytes = cv.off;
-    cv.take<unsigned long long>(4);
-    cv.take<uint32_t>(4);
-    cv.take<uint64_t>((size_t)Cg * n);
-    cv.take<uint32_t>((size_t)Cg * nt * nb);
-    cv.take<uint32_t>(hier_cand ? (size_t)(PROBE_HIER + PROBE_STD + 1) * PROBE_BINS : 1);
-    cv.take<unsigned long long>(1);
-    cv.take<uint32_t>((size_t)Cg * (nb + 1));
-    cv.take<Ovf>((size_t)Cg * nb);
-    cv.take<Ovf>((size_t)Cg * nb);
-    cv.take<uint64_t>((size_t)Cg * nb + 1);
-    void* scr = nullptr;
-    msm_status st = msm::scratch(ctx, cv.off, stream, &scr);
-    if (st != MSM_OK) return st;
+    void* scr = ext;
+    if (!ext) {
+        msm_status st = msm::ctx_scratch(ctx, bytes_for(Cg), stream, &scr);
+        if (st != MSM_OK) return st;
+    }
     msm::Carver c2;
     c2.base = static_cast<char*>(scr);
-    Combo* d_combos_std = c2.take<Combo>((size_t)Cstd);
-    Combo* d_combos_h = c2.take<Combo>((size_t)std::max(1, Ch));
-    Combo* d_full = c2.take<Combo>(1);
-    uint64_t* d_fam = c2.take<uint64_t>(std::max<size_t>(1, fam.size()));
-    uint32_t* d_dtab = c2.take<uint32_t>(std::max<size_t>(1, dtab.size()));
-    uint64_t* d_bm = c2.take<uint64_t>((size_t)k * MAXW);
-    unsigned long long* d_counter = c2.take<unsigned long long>(4);
-    uint32_t* d_ovfc = c2.take<uint32_t>(4);
-    uint64_t* d_part = c2.take<uint64_t>((size_t)Cg * n);
-    uint32_t* d_counts = c2.take<uint32_t>((size_t)Cg * nt * nb);
-    uint32_t* d_probe = c2.take<uint32_t>(hier_cand ? (size_t)(PROBE_HIER + PROBE_STD + 1) * PROBE_BINS : 1);
-    unsigned long long* d_work = c2.take<unsigned long long>(1);
-    uint32_t* d_base = c2.take<uint32_t>((size_t)Cg * (nb + 1));
-    Ovf* d_ovf = c2.take<Ovf>((size_t)Cg * nb);
-    Ovf* d_ovf2 = c2.take<Ovf>((size_t)Cg * nb);
-    uint64_t* d_tile0 = c2.take<uint64_t>((size_t)Cg * nb + 1);
+    const EnumMem mem = carve_enum(c2, Cstd, Ch, fam.size(), dtab.size(), k, hier_cand, Cg, n, nt, nb);
+    const size_t table_bytes = mem.table_bytes;
+    if (ext && table_bytes > msm::NOALLOC_STAGE_BYTES)
+        return msm::fail(ctx, MSM_E_UNSUPPORTED,
+                         "msm_enumerate_pairs_noalloc: %zu bytes of tables for k=%d, h=%d exceed the %zu-byte "
+                         "staging buffer",
+                         table_bytes, k, h, msm::NOALLOC_STAGE_BYTES);
+    Combo* d_combos_std = mem.combos_std;
+    Combo* d_combos_h = mem.combos_h;
+    Combo* d_full = mem.full;
+    uint64_t* d_fam = mem.fam;
+    uint32_t* d_dtab = mem.dtab;
+    uint64_t* d_bm = mem.bm;
+    unsigned long long* d_counter = mem.counter;
+    uint32_t* d_ovfc = mem.ovfc;
+    uint64_t* d_part = mem.part;
+    uint32_t* d_counts = mem.counts;
+    uint32_t* d_probe = mem.probe;
+    unsigned long long* d_work = mem.work;
+    uint32_t* d_base = mem.base;
+    Ovf* d_ovf = mem.ovf;
+    Ovf* d_ovf2 = mem.ovf2;
+    uint64_t* d_tile0 = mem.tile0;
 
     {
         Combo full{};  // the whole string kept: groups of identical strings
         for (int w = 0; w < MAXW; ++w) full.keep[w] = valid[w];
-        std::vector<char> blob(table_bytes, 0);
+        // pageable host memory, or the pinned staging buffer when nothing may
+        // be allocated (the call synchronises the stream before it returns,
+        // so the copy has read the buffer before its next use)
+        std::vector<char> own(ext ? 0 : table_bytes, 0);
+        char* blob = ext ? ctx->host_stage : own.data();
+        if (ext) std::memset(blob, 0, table_bytes);
         auto put = [&](const void* dev, const void* src, size_t bytes) {
-            if (bytes) std::memcpy(blob.data() + (static_cast<const char*>(dev) - c2.base), src, bytes);
+            if (bytes) std::memcpy(blob + (static_cast<const char*>(dev) - c2.base), src, bytes);
         };
         put(d_combos_std, combos.data(), sizeof(Combo) * Cstd);
         put(d_combos_h, parts.data(), sizeof(Combo) * Ch);
@@ -141,8 +206,7 @@ msm_status run_enumerate(msm_ctx* ctx, const uint64_t* S, int64_t n, int ell, in
         put(d_fam, fam.data(), sizeof(uint64_t) * fam.size());
         put(d_dtab, dtab.data(), sizeof(uint32_t) * dtab.size());
         put(d_bm, bm.data(), sizeof(uint64_t) * bm.size());
-        MSM_HIP(ctx, hipMemcpyAsync(c2.base, blob.data(), table_bytes, hipMemcpyHostToDevice, stream));
-        // the copy is from pageable memory: it has read blob on return
+        MSM_HIP(ctx, hipMemcpyAsync(c2.base, blob, table_bytes, hipMemcpyHostToDevice, stream));
     }
     hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, stream, d_counter, 4);
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, stream, d_ovfc, 4);
@@ -294,7 +358,7 @@ msm_status run_enumerate(msm_ctx* ctx, const uint64_t* S, int64_t n, int ell, in
 
 static msm_status enumerate_entry(const char* fn, msm_ctx* ctx, const uint64_t* S, int64_t n, int32_t ell,
                                   int32_t Q, int32_t k, int32_t h, uint32_t* pairs, int64_t cap, int64_t* m_out,
-                                  void* stream)
+                                  void* stream, bool noalloc = false)
 {
     if (!ctx) return msm::fail(nullptr, MSM_E_INVALID, "%s: ctx is NULL", fn);
     ctx->err.clear();
@@ -317,11 +381,19 @@ static msm_status enumerate_entry(const char* fn, msm_ctx* ctx, const uint64_t* 
     msm_status st = msm::use_device(ctx);
     if (st != MSM_OK) return st;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    void* ext = nullptr;
+    size_t ext_bytes = 0;
+    if (noalloc) {
+        if (!ctx->noalloc_scratch || !ctx->host_stage)
+            return msm::fail(ctx, MSM_E_UNSUPPORTED, "%s: no static scratch on device %d", fn, ctx->device);
+        ext = ctx->noalloc_scratch;
+        ext_bytes = msm::NOALLOC_SCRATCH_BYTES;
+    }
     switch ((ell + 63) / 64) {
-        case 1: return run_enumerate<1>(ctx, S, n, ell, Q, k, h, pairs, cap, m_out, s);
-        case 2: return run_enumerate<2>(ctx, S, n, ell, Q, k, h, pairs, cap, m_out, s);
-        case 3: return run_enumerate<3>(ctx, S, n, ell, Q, k, h, pairs, cap, m_out, s);
-        default: return run_enumerate<4>(ctx, S, n, ell, Q, k, h, pairs, cap, m_out, s);
+        case 1: return run_enumerate<1>(ctx, S, n, ell, Q, k, h, pairs, cap, m_out, s, ext, ext_bytes);
+        case 2: return run_enumerate<2>(ctx, S, n, ell, Q, k, h, pairs, cap, m_out, s, ext, ext_bytes);
+        case 3: return run_enumerate<3>(ctx, S, n, ell, Q, k, h, pairs, cap, m_out, s, ext, ext_bytes);
+        default: return run_enumerate<4>(ctx, S, n, ell, Q, k, h, pairs, cap, m_out, s, ext, ext_bytes);
     }
 }
 
@@ -330,6 +402,13 @@ extern "C" msm_status msm_enumerate_pairs(msm_ctx* ctx, const uint64_t* S, int64
                                           int64_t* m_out, void* stream)
 {
     return enumerate_entry("msm_enumerate_pairs", ctx, S, n, ell, 1, k, h, pairs, cap, m_out, stream);
+}
+
+extern "C" msm_status msm_enumerate_pairs_noalloc(msm_ctx* ctx, const uint64_t* S, int64_t n, int32_t ell,
+                                                  int32_t k, int32_t h, uint32_t* pairs, int64_t cap,
+                                                  int64_t* m_out, void* stream)
+{
+    return enumerate_entry("msm_enumerate_pairs_noalloc", ctx, S, n, ell, 1, k, h, pairs, cap, m_out, stream, true);
 }
 
 extern "C" msm_status msm_enumerate_replicates(msm_ctx* ctx, const uint64_t* S, int64_t n, int32_t ell,

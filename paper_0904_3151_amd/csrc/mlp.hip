@@ -689,7 +689,7 @@ extern "C" msm_status msm_project_mlp(msm_ctx* ctx, const float* X, int64_t n, i
         cv.take<float>((size_t)nch * FU_HC);
         cv.take<float>((size_t)Np);
         void* scr = nullptr;
-        st = msm::scratch(ctx, cv.off, s, &scr);
+        st = msm::ctx_scratch(ctx, cv.off, s, &scr);
         if (st != MSM_OK) return st;
         msm::Carver c2;
         c2.base = static_cast<char*>(scr);
@@ -720,7 +720,7 @@ extern "C" msm_status msm_project_mlp(msm_ctx* ctx, const float* X, int64_t n, i
     cv.take<float>((size_t)rows_max * hid);
     cv.take<float>((size_t)rows_max * hid);
     void* scr = nullptr;
-    st = msm::scratch(ctx, cv.off, s, &scr);
+    st = msm::ctx_scratch(ctx, cv.off, s, &scr);
     if (st != MSM_OK) return st;
     msm::Carver c2;
     c2.base = static_cast<char*>(scr);
@@ -773,7 +773,7 @@ extern "C" msm_status msm_mlp_loss_grad(msm_ctx* ctx, const float* X, int64_t n,
     TrainBufs tb;
     const size_t bytes = train_carve(cv, 2ll * B, d, hid, ell, &tb);
     void* scr = nullptr;
-    st = msm::scratch(ctx, bytes, s, &scr);
+    st = msm::ctx_scratch(ctx, bytes, s, &scr);
     if (st != MSM_OK) return st;
     msm::Carver c2;
     c2.base = static_cast<char*>(scr);
@@ -844,7 +844,7 @@ extern "C" msm_status msm_mlp_train(msm_ctx* ctx, const float* X, int64_t n, int
     TrainBufs tb;
     const size_t bytes = train_carve(cv, 2ll * B, d, hid, ell, &tb);
     void* scr = nullptr;
-    st = msm::scratch(ctx, bytes, s, &scr);
+    st = msm::ctx_scratch(ctx, bytes, s, &scr);
     if (st != MSM_OK) return st;
     msm::Carver c2;
     c2.base = static_cast<char*>(scr);

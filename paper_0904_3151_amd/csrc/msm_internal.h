@@ -23,6 +23,13 @@ struct msm_ctx {
     size_t scratch_bytes = 0;
     // Pinned host words used to read counters back from the device.
     uint64_t* host_words = nullptr;
+    // Pinned host staging for table uploads of the calls that allocate
+    // nothing (NOALLOC_STAGE_BYTES).
+    char* host_stage = nullptr;
+    // Device address, on this context's device, of the library's static
+    // no-allocation scratch (NOALLOC_SCRATCH_BYTES), or NULL when it could
+    // not be resolved.
+    void* noalloc_scratch = nullptr;
     // Groupings (and j of a hierarchical grouping, else 0) of the last
     // enumeration.
     int32_t last_groupings = 0;
@@ -41,13 +48,19 @@ struct msm_ctx {
 
 namespace msm {
 
+// Size of the static device array that msm_enumerate_pairs_noalloc works in
+// (one per device, held until the process ends), and of the pinned host
+// buffer through which that call uploads its tables.
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)64 << 20;
+constexpr size_t NOALLOC_STAGE_BYTES = (size_t)2 << 20;
+
 msm_status fail(msm_ctx* ctx, msm_status st, const char* fmt, ...);
 msm_status hip_fail(msm_ctx* ctx, hipError_t e, const char* what);
 // Make the device of ctx current.
 msm_status use_device(msm_ctx* ctx);
 // Device scratch of at least `bytes` (256-byte aligned). Synchronises
 // `stream` before replacing a smaller buffer.
-msm_status scratch(msm_ctx* ctx, size_t bytes, hipStream_t stream, void** out);
+msm_status ctx_scratch(msm_ctx* ctx, size_t bytes, hipStream_t stream, void** out);
 
 // Records a HIP event before and after the launches in its scope, on the
 // launch stream, when profiling is on.

@@ -405,7 +405,7 @@ msm_status launch_lp(msm_ctx* ctx, const float* X, int64_t n, int d, int64_t ldx
     cv.take<BT>((size_t)nkc * NCB * 64);
     cv.take<float>((size_t)ell * d);
     void* scr = nullptr;
-    msm_status st = msm::scratch(ctx, cv.off, stream, &scr);
+    msm_status st = msm::ctx_scratch(ctx, cv.off, stream, &scr);
     if (st != MSM_OK) return st;
     msm::Carver c2;
     c2.base = static_cast<char*>(scr);

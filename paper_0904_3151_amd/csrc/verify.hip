@@ -258,7 +258,7 @@ extern "C" msm_status msm_verify(msm_ctx* ctx, const float* X, int64_t n, int32_
     if (st != MSM_OK) return st;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     void* scr = nullptr;
-    st = msm::scratch(ctx, 256, s, &scr);
+    st = msm::ctx_scratch(ctx, 256, s, &scr);
     if (st != MSM_OK) return st;
     unsigned long long* counter = static_cast<unsigned long long*>(scr);
     uint32_t* bad = reinterpret_cast<uint32_t*>(counter + 1);

@@ -39,7 +39,8 @@ DTYPES = {"f32": F32, "bf16": BF16, "fp8": FP8_E4M3, "fp8_e4m3": FP8_E4M3}
 METRICS = {"euclidean": EUCLIDEAN, "cosine": COSINE}
 
 EXPORTS = ("msm_version", "msm_create", "msm_destroy", "msm_last_error",
-           "msm_project", "msm_project_lowp", "msm_enumerate_pairs", "msm_enumerate_replicates", "msm_enumerate_groupings",
+           "msm_project", "msm_project_lowp", "msm_enumerate_pairs", "msm_enumerate_pairs_noalloc",
+           "msm_enumerate_replicates", "msm_enumerate_groupings",
            "msm_enumerate_last_plan",
            "msm_verify", "msm_bruteforce_eps",
            "msm_project_mlp", "msm_mlp_loss_grad", "msm_mlp_adam", "msm_mlp_train",
@@ -95,6 +96,8 @@ def _load():
     lib.msm_project_lowp.restype = i32
     lib.msm_enumerate_pairs.argtypes = [vp, vp, i64, i32, i32, i32, vp, i64, ctypes.POINTER(i64), vp]
     lib.msm_enumerate_pairs.restype = i32
+    lib.msm_enumerate_pairs_noalloc.argtypes = [vp, vp, i64, i32, i32, i32, vp, i64, ctypes.POINTER(i64), vp]
+    lib.msm_enumerate_pairs_noalloc.restype = i32
     lib.msm_enumerate_replicates.argtypes = [vp, vp, i64, i32, i32, i32, i32, vp, i64, ctypes.POINTER(i64), vp]
     lib.msm_enumerate_replicates.restype = i32
     lib.msm_enumerate_groupings.argtypes = [i64, i32, i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]
@@ -270,6 +273,26 @@ def msm_enumerate_pairs(ctx: Context, S: torch.Tensor, ell: int, k: int, h: int,
     m = ctypes.c_int64(0)
     st = _lib.msm_enumerate_pairs(ctx.handle, _ptr(S), n, int(ell), int(k), int(h), _ptr(pairs), cap,
                                   ctypes.byref(m), _stream(stream))
+    _check(ctx, st, m.value)
+    return (pairs[: m.value] if pairs is not None else None), m.value
+
+
+def msm_enumerate_pairs_noalloc(ctx: Context, S: torch.Tensor, ell: int, k: int, h: int,
+                                pairs: torch.Tensor | None = None, cap: int | None = None, stream=None):
+    """msm_enumerate_pairs computed in the library's fixed per-device buffer
+    (no allocation inside the call); same results and conventions."""
+    assert S.dtype == torch.int64 and S.dim() == 2 and S.is_contiguous() and S.is_cuda
+    n = S.shape[0]
+    assert S.shape[1] == _words(ell)
+    if pairs is None:
+        cap = 0 if cap is None else int(cap)
+        assert cap == 0, "pass a preallocated pairs tensor"
+    else:
+        assert pairs.dtype == torch.int32 and pairs.is_contiguous() and pairs.dim() == 2
+        cap = pairs.shape[0] if cap is None else int(cap)
+    m = ctypes.c_int64(0)
+    st = _lib.msm_enumerate_pairs_noalloc(ctx.handle, _ptr(S), n, int(ell), int(k), int(h), _ptr(pairs), cap,
+                                          ctypes.byref(m), _stream(stream))
     _check(ctx, st, m.value)
     return (pairs[: m.value] if pairs is not None else None), m.value
 
