@@ -350,7 +350,9 @@ msm_status msm_batch_create(msm_ctx* ctx, const msm_instance* inst, int32_t coun
 msm_status msm_batch_run(msm_batch* b, int64_t* m_dev, void* stream);
 
 /* msm_batch_run captured once into a HIP graph (on the plan's own stream;
- * again whenever m_dev changes) and launched on `stream` as one graph. */
+ * again whenever m_dev changes) and launched on `stream` as one graph. A
+ * re-capture for a new m_dev first waits for the previous graph launch to
+ * finish (an event recorded after each launch), whichever stream it ran on. */
 msm_status msm_batch_launch_graph(msm_batch* b, int64_t* m_dev, void* stream);
 
 /* The configuration in use and, when the plan was tuned, every candidate

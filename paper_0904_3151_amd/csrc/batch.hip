@@ -88,9 +88,16 @@ struct msm_batch {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int64_t* graph_m = nullptr;
+    // recorded on the caller's stream after each graph launch: the exec is
+    // only destroyed once its last launch has finished
+    hipEvent_t graph_done = nullptr;
 
     ~msm_batch()
     {
+        if (graph_done) {
+            (void)hipEventSynchronize(graph_done);
+            (void)hipEventDestroy(graph_done);
+        }
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
@@ -475,6 +482,7 @@ extern "C" msm_status msm_batch_create(msm_ctx* ctx, const msm_instance* inst, i
     MSM_HIP(ctx, hipMemcpy(b->d_combos, b->combos.data(), sizeof(Combo) * b->C, hipMemcpyHostToDevice));
     MSM_HIP(ctx, hipMemcpy(b->d_bm, b->bm.data(), sizeof(uint64_t) * b->bm.size(), hipMemcpyHostToDevice));
     MSM_HIP(ctx, hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+    MSM_HIP(ctx, hipEventCreateWithFlags(&b->graph_done, hipEventDisableTiming));
     {
         // the partition scatter stages a whole tile and two words per bucket in LDS
         const int lds = BATCH_T * 8 + (1 << MAX_R) * 8;
@@ -529,7 +537,8 @@ extern "C" msm_status msm_batch_launch_graph(msm_batch* b, int64_t* m_dev, void*
     if (st != MSM_OK) return st;
     if (!b->exec || b->graph_m != m_dev) {
         if (b->exec) {
-            MSM_HIP(ctx, hipStreamSynchronize(b->cap_stream));
+            // the old exec was launched on a caller's stream: wait for it
+            MSM_HIP(ctx, hipEventSynchronize(b->graph_done));
             MSM_HIP(ctx, hipGraphExecDestroy(b->exec));
             b->exec = nullptr;
         }
@@ -554,6 +563,7 @@ extern "C" msm_status msm_batch_launch_graph(msm_batch* b, int64_t* m_dev, void*
     std::unique_ptr<msm::KernelTimer> kt;
     if (ctx->prof) kt.reset(new msm::KernelTimer(ctx, s, "batch_graph"));
     MSM_HIP(ctx, hipGraphLaunch(b->exec, s));
+    MSM_HIP(ctx, hipEventRecord(b->graph_done, s));
     return MSM_OK;
 }
 

@@ -162,6 +162,11 @@ struct BatchArgs {
     unsigned long long* m_dev;    // per-instance pair counters
 };
 
+// The output finalizer of SplitMix64 (Steele, Lea and Flood, "Fast
+// splittable pseudorandom number generators", OOPSLA 2014), with its
+// published shift and multiplier constants: a bijection of 64-bit words
+// whose output bits each depend on every input bit. Used only to spread
+// masked strings over buckets; equal strings always get equal mixes.
 __device__ __forceinline__ uint64_t mix64(uint64_t z)
 {
     z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;

@@ -138,17 +138,27 @@ def projection_matrices(d: int, ell: int, Q: int, seed: int) -> np.ndarray:
     return np.stack([projection_matrix(d, ell, seed + 100 * q) for q in range(Q)])
 
 
+def batched_sizes(count: int, seed: int, n_lo: int = 1000, n_hi: int = 200_000, ds=(32, 64, 128)):
+    """Sizes of the batched form's instances: n log-uniform in [n_lo, n_hi]
+    and d uniform over ds. Returns (ns int64, ds int64), one entry each."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ns = np.exp(rng.uniform(np.log(n_lo), np.log(n_hi), count)).astype(np.int64)
+    dd = rng.choice(np.asarray(ds), count).astype(np.int64)
+    return ns, dd
+
+
 def batched_instances(count: int, seed: int, n_lo: int = 1000, n_hi: int = 200_000,
-                      ds=(32, 64, 128), ell: int = 64, sigma: float = 0.2):
+                      ds=(32, 64, 128), ell: int = 64, sigma: float = 0.2, select=None):
     """Sizes and inputs of independent instances for the batched form:
     n log-uniform in [n_lo, n_hi], d uniform over ds, Gaussian-mixture rows
     with n / 100 clusters (at least one) and per-coordinate sigma, and an
-    N(0, 1) projection matrix per instance. Returns a list of (X, R)."""
-    rng = np.random.Generator(np.random.PCG64(seed))
-    ns = np.exp(rng.uniform(np.log(n_lo), np.log(n_hi), count)).astype(np.int64)
-    dd = rng.choice(np.asarray(ds), count)
+    N(0, 1) projection matrix per instance. Returns a list of (X, R).
+
+    ``select`` draws only the listed instances of the `count`; instance i is
+    the same array whichever others are drawn with it."""
+    ns, dd = batched_sizes(count, seed, n_lo, n_hi, ds)
     out = []
-    for i in range(count):
+    for i in (range(count) if select is None else select):
         n, d = int(ns[i]), int(dd[i])
         X, _ = gaussian_mixture(n, d, max(1, n // 100), sigma, seed=seed * 1000 + i)
         out.append((X, projection_matrix(d, ell, seed=seed * 1000 + 500_000 + i)))

@@ -159,3 +159,53 @@ def test_batch_invalid(msm, ctx):
     assert st == msm.MSM_E_INVALID and not h_.value
     st = msm.lib().msm_batch_create(ctx.handle, arr, 0, 64, 5, 3, 0, ctypes.byref(h_), None)
     assert st == msm.MSM_E_INVALID
+
+
+def test_batch_workload_instances_match_oracle(msm, ctx):
+    """Instances of the batched workload itself (512 instances, seed 1004),
+    at its sizes: nine that span two to five partition tiles
+    (4 276 <= n <= 19 483) are compared in full with the exhaustive Hamming
+    pairs of their strings, and the largest (199 548 points) on every
+    Hamming partner of 64 sampled rows over all of its points, plus the
+    invariants of its whole output; strings are checked against the FP64
+    projection on sampled rows."""
+    ell, k, h = 64, 5, 3
+    ns, _ = I.batched_sizes(512, 1004)
+    mid = [3, 7, 8, 13, 14, 21, 22, 27, 40]
+    big = int(np.argmax(ns))
+    assert all(4096 < ns[i] <= 20_000 for i in mid) and ns[big] > 150_000
+    sel = mid + [big]
+    inst = I.batched_instances(512, 1004, ell=ell, select=sel)
+    Xs, Rs = upload(inst)
+    caps = [60 * X.shape[0] for X, _ in inst]
+    announce("batch workload instances", [X.shape for X, _ in inst])
+    b = msm.Batch(ctx, Xs, Rs, ell, k, h, caps, autotune=True)
+    m = b.run().cpu().numpy()
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(21)
+    for q, (X, R) in enumerate(inst):
+        n = X.shape[0]
+        assert m[q] <= caps[q], (sel[q], m[q], caps[q])
+        S = to_np_strings(b.S[q])
+        rows = np.sort(rng.choice(n, size=min(n, 2000), replace=False))
+        So, Z, xn = O.project(X, R, rows=rows, want_z=True)
+        bad = I.unpack_bits(S[rows], ell) != I.unpack_bits(So, ell)
+        assert not (bad & ~(np.abs(Z) < PROJ_BAND * xn[:, None])).any(), f"instance {sel[q]}: bits"
+        P = b.instance_pairs(q, m[q])
+        if n <= 20_000:
+            want = codes(O.hamming_pairs(S, h))
+            got = codes(to_np_pairs(P))
+            assert m[q] == want.size and np.array_equal(got, want), f"instance {sel[q]} (n={n})"
+            continue
+        i = P[:, 0].to(torch.int64)
+        j = P[:, 1].to(torch.int64)
+        assert bool((i < j).all()) and bool((i >= 0).all()) and bool((j < n).all())
+        c, _ = torch.sort(i * n + j)
+        assert not bool((c[1:] == c[:-1]).any()), "duplicate pairs"
+        probe = np.sort(rng.choice(n, size=64, replace=False))
+        want = codes(O.hamming_partners(S, h, probe))
+        pt = torch.from_numpy(probe).cuda()
+        sel_rows = torch.isin(i, pt) | torch.isin(j, pt)
+        got = codes(to_np_pairs(P[sel_rows].contiguous()))
+        assert want.size > 0 and np.array_equal(got, want), (sel[q], got.size, want.size)
+    b.close()

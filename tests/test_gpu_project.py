@@ -63,6 +63,24 @@ def test_project_shapes(msm, ctx, n, d, ell, pad, off):
     check(msm, ctx, X, R, pad, off)
 
 
+def test_project_split_form_many_tiles_sampled_rows(msm, ctx):
+    """100 000 rows at d = 200, ell = 96: the split form's eight-chunk path
+    over many row tiles per workgroup (its prefetch of the next tile's rows),
+    checked on 4 000 sampled rows against the FP64 projection."""
+    n, d, ell = 100_000, 200, 96
+    X, _ = I.gaussian_mixture(n, d, 500, 0.2, seed=77, sigma_mode="coord")
+    R = I.projection_matrix(d, ell, seed=78)
+    announce("project sampled", n, d, ell)
+    S = msm.msm_project(ctx, torch.from_numpy(X).cuda(), torch.from_numpy(R).cuda())
+    torch.cuda.synchronize()
+    Sg = to_np_strings(S)
+    rows = I.subsample_indices(n, 4000, seed=79)
+    rows = np.union1d(rows, [0, n - 1])
+    So, Z, xn = O.project(X, R, rows=rows, want_z=True)
+    bad = (I.unpack_bits(Sg[rows], ell) != I.unpack_bits(So, ell)) & ~(np.abs(Z) < PROJ_BAND * xn[:, None])
+    assert not bad.any(), f"{bad.sum()} bits differ outside the band"
+
+
 def test_project_zero_rows_and_sparse(msm, ctx):
     rng = np.random.default_rng(8)
     X = (rng.random((600, 64)) < 0.05) * rng.lognormal(0, 1, (600, 64))

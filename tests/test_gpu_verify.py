@@ -67,6 +67,33 @@ def test_verify_shapes_scalar_path(msm, ctx, d, offset):
     check(msm, ctx, X, _all_pairs(1500), O.EUCLIDEAN, 0.12, offset)
 
 
+@pytest.mark.parametrize("d", [4, 36, 100, 160, 192, 228])
+@pytest.mark.parametrize("metric,eps", [(O.EUCLIDEAN, 0.15), (O.COSINE, 0.004)])
+def test_verify_aligned_widths(msm, ctx, d, metric, eps):
+    """Aligned rows from one to eight 32-float steps of a team (the last
+    one partial or the ragged tail), on pair lists in the order the
+    enumeration writes them: runs of pairs that share their first point, of
+    lengths one to forty. One list pairs points with cluster mates (mostly
+    near, the straight loop), one with random points (mostly far, the
+    early-rejection mode)."""
+    X, lab = I.gaussian_mixture(1200, d, 25, 0.1, seed=d, sigma_mode="radius")
+    rng = np.random.default_rng(d)
+    for mates in (True, False):
+        runs = []
+        for a in range(0, 1199, 3):
+            pool = np.arange(a + 1, 1200)
+            if mates:
+                pool = pool[lab[a + 1:] == lab[a]]
+            ln = min(int(rng.integers(1, 40)), pool.size)
+            if ln == 0:
+                continue
+            js = np.sort(rng.choice(pool, size=ln, replace=False))
+            runs.append(np.stack([np.full(js.size, a), js], 1))
+        pairs = np.concatenate(runs).astype(np.uint32)
+        kept, _ = check(msm, ctx, X, pairs, metric, eps)
+        assert kept > 0
+
+
 def test_verify_cosine_sparse_with_zero_rows(msm, ctx):
     rng = np.random.default_rng(4)
     n, d = 2000, 64
@@ -128,3 +155,31 @@ def test_verify_early_rejection_mixed(msm, ctx, d):
     far = head[~np.isin(codes(head), codes(near))]
     order = np.concatenate([near, far])
     check(msm, ctx, X, order, O.EUCLIDEAN, 0.03)
+
+
+def test_verify_cosine_precision_shape_with_zero_rows(msm, ctx):
+    """The precision workload's rows (d = 256, 5 % support, lognormal
+    values, unit norm, rows without support left at zero), cosine distance:
+    all pairs of 2 500 rows plus a list of near pairs (rows sharing most of
+    their support), at the workload's eps and two wider ones. A pair with a
+    zero row is never kept."""
+    n, d = 2500, 256
+    X = I.sparse_lognormal(n, d, 0.05, seed=1003)
+    rng = np.random.default_rng(31)
+    # near copies: a row with 10 % noise on its own support
+    src = rng.choice(np.arange(1, n, 2), size=300, replace=False)
+    for a in src:
+        y = X[a] * (1.0 + 0.1 * rng.standard_normal(d).astype(np.float32))
+        nrm = np.linalg.norm(y)
+        X[(a + 1) % n] = y / nrm if nrm > 0 else 0.0
+    X[::83] = 0.0
+    pairs = _all_pairs(n)
+    for eps in (0.2, 0.6, 0.95):
+        kept, _ = check(msm, ctx, X, pairs, O.COSINE, eps)
+        assert kept > 0
+    zero = np.arange(0, n, 83, dtype=np.uint32)
+    zp = np.stack([zero, (zero + 1) % n], 1).astype(np.uint32)
+    zp = np.sort(zp, axis=1)
+    Pd = torch.from_numpy(np.ascontiguousarray(zp).view(np.int32)).cuda()
+    _, kz = msm.msm_verify(ctx, torch.from_numpy(X).cuda(), Pd, O.COSINE, 0.99)
+    assert kz == 0
