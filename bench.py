@@ -1,23 +1,30 @@
 """Benchmark of the whole path on one GPU: project, enumerate, verify.
 
-One step = msm_project + msm_enumerate_pairs + msm_verify over the paper-scale
-mixture (n = 1,000,000, d = 128, ell = 128 bits, k = 8 blocks, h = 4,
-Euclidean eps = 0.5), inputs already resident in device memory. Prints one
-JSON line. ``value`` is points per second of whole steps. The run is repeated
-under the other reading of the mixture's sigma (per-coordinate standard
-deviation, or cluster radius), under which the epsilon graph is not empty
-and the missing-edge ratio is defined.
+One step = msm_project (one call per string pool) + the enumeration
+(msm_enumerate_pairs, or msm_enumerate_replicates over Q pools) +
+msm_verify, over the paper-scale mixture (n = 1,000,000, d = 128, ell = 128
+bits, k = 8 blocks, h = 4, Euclidean eps = 0.5), inputs already resident in
+device memory. Prints one JSON line. ``value`` is points per second of whole
+steps at the headline reading: clusters of radius sigma (the reading under
+which the epsilon graph is not empty), with the least number Q of string
+pools whose missing-edge ratio against the exhaustive reference on the
+50 000-point subsample is at most 1e-3 (Section 4.1, eq. (5)).
 
-Other workloads: ``--workload precision`` (4M sparse cosine rows, FP32 /
-BF16 / FP8 projections) and ``--workload learned`` (2M mixture points, the
-learned projection trained on the GPU against random projection) and
-``--workload batched`` (512 independent instances in one captured graph)
-and ``--workload sweep`` (output sensitivity: n from 125k to 2M, and the
-all-identical worst case).
+The same line carries the other forms side by side, each with its
+missing-edge ratio, points/s, edges/s and the roofline of its dominant
+kernel: the single-pool step at the same reading, the per-coordinate
+reading of sigma (whose epsilon graph is empty), the precision form (4M
+sparse cosine rows with FP32 / BF16 / FP8 projections), the learned
+projection (2M mixture points, network trained on the GPU, against random
+projection at equal ell) and a summary of the output-sensitivity sweep.
 
-Usage: python bench.py [--steps K] [--warmup W] [--sigma-mode coord|radius]
-                       [--cpu-sample N | --no-cpu-baseline] [--no-second-reading]
-                       [--workload paper|precision|learned|batched|sweep] [--epochs E]
+Dedicated runs: ``--workload precision|learned|batched|sweep`` print one
+line for that form alone (batched: 512 independent instances in one
+captured graph; sweep: n from 125k to 2M and the all-identical worst case).
+
+Usage: python bench.py [--steps K] [--warmup W] [--cpu-sample N | --no-cpu-baseline]
+                       [--headline-only] [--workload paper|precision|learned|batched|sweep]
+                       [--epochs E] [--q-max Q]
 """
 import argparse
 import json
@@ -82,27 +89,34 @@ def copy_calibration(nbytes, reps=3):
     print(json.dumps({"copy_bytes": n * 4, "reps": reps}), flush=True)
 
 
-def algorithmic(kernel, w, n, C, mH, mE, W):
+def algorithmic(kernel, w, n, C, mH, mE, W, launches=1, hid=None):
     """(amount, unit, bound) of algorithmic work per launch of a kernel.
 
     Units per launch: a launch of the partition and bucket kernels covers n
     points under each of the C groupings (C(k, h) combinations of masked
-    blocks, or the hierarchical groupings that replace them); k_verify covers the mH
-    candidate pairs and the n rows; k_project_f32 the n x d x ell products
-    (k_project_x3 makes each of them as six BF16 products).
+    blocks, or the hierarchical groupings that replace them) of one string
+    pool, and writes its share (1 / `launches`) of the mH pairs; k_verify
+    covers the mH candidate pairs and the n rows; k_project_f32 the
+    n x d x ell products (k_project_x3 makes each of them as six BF16
+    products); the low-precision projections read X once; k_mlp_fused makes
+    the network's 2 n (d hid + hid ell) products.
     """
     sb = 8 * W  # bytes of one string
     if kernel == "k_project_f32":
         return 2.0 * n * w.d * w.ell / 1e12, "TFLOP/s", "mfma"
     if kernel == "k_project_x3":
         return 6 * 2.0 * n * w.d * w.ell / 1e12, "TFLOP/s", "mfma_bf16"
+    if kernel in ("k_project_bf16", "k_project_fp8"):
+        return (n * 4 * w.d + n * sb) / 1e9, "GB/s", "hbm"
+    if kernel == "k_mlp_fused" and hid:
+        return 2.0 * n * (w.d * hid + hid * w.ell) / 1e12, "TFLOP/s", "mfma_bf16"
     if kernel == "k_part_count":
         return n * C * sb / 1e9, "GB/s", "hbm"
     if kernel == "k_part_scatter":
         return n * C * (sb + 8) / 1e9, "GB/s", "hbm"
     if kernel == "k_bucket":
         # per point and combination: its 8-byte partition entry and its string
-        return (n * C * (8 + sb) + mH * 8) / 1e9, "GB/s", "hbm"
+        return (n * C * (8 + sb) + mH * 8 / max(launches, 1)) / 1e9, "GB/s", "hbm"
     if kernel == "k_verify":
         # compulsory traffic: candidate pairs in, kept pairs out, each row
         # of X once (the two rows of every candidate are re-read through the
@@ -146,21 +160,40 @@ def missing_edge_ratio(msm, ctx, w, Xd, hamming, verified, sub=None):
             "note": None if mstar else "no pair of the subsample is within eps"}
 
 
-def cpu_baseline(w, X, R, sample):
-    """The oracle (FP64 project, MSM, verify) on the first `sample` rows."""
+def host_cpu():
+    """Model name of the host CPU (first 'model name' of /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(w, X, Rs, sample, Q=1):
+    """The oracle (FP64 project, MSM per pool, union, verify) on the first
+    `sample` rows: the same step as the GPU's, with Q string pools."""
     import numpy as np
 
     from oracle import oracle as O
     Xs = np.ascontiguousarray(X[:sample])
+    metric = O.EUCLIDEAN if w.metric == "euclidean" else O.COSINE
     t0 = time.perf_counter()
-    S = O.project(Xs, R)
-    P = O.msm(S, w.ell, w.k, w.h)
-    O.verify(Xs, P, O.EUCLIDEAN, float(np.float32(w.eps)))
+    codes = []
+    for q in range(Q):
+        S = O.project(Xs, Rs[q])
+        codes.append(O.pair_codes(O.msm(S, w.ell, w.k, w.h)))
+    u = np.unique(np.concatenate(codes)) if codes else np.zeros(0, np.uint64)
+    P = np.stack([(u >> np.uint64(32)).astype(np.uint32), (u & np.uint64(0xFFFFFFFF)).astype(np.uint32)], 1)
+    O.verify(Xs, P, metric, float(np.float32(w.eps)))
     t = time.perf_counter() - t0
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
     what = "all" if sample == w.n else f"first {sample} of"
-    return {"value": sample / t, "unit": "points/s", "cores": threads, "kind": "oracle",
-            "sample": f"{what} {w.n} points, one full step (FP64 project + MSM + verify), {t:.1f} s"}
+    return {"value": sample / t, "unit": "points/s", "cores": threads, "kind": "oracle", "cpu": host_cpu(),
+            "sample": f"{what} {w.n} points, one full step (FP64 project of {Q} pool(s) + MSM + union "
+                      f"+ verify), {t:.1f} s"}
 
 
 def flip_rate(X, R, S_dev, rows):
@@ -179,109 +212,41 @@ def flip_rate(X, R, S_dev, rows):
     return float(bad.mean()), float((bad & ~band).mean())
 
 
-def run_precision(args):
-    """The precision form: 4M sparse cosine rows projected in FP32, BF16 and
-    row-scaled FP8 (FP32 recompute inside |z| < 2^-8 |x|), then the same
-    enumeration and verification. One JSON line with every dtype."""
-    import numpy as np
-    import torch
-
-    from paper_0904_3151_amd import inputs as I
-    from paper_0904_3151_amd import msm
-
-    w = I.PRECISION
-    log(f"generating {w.name}")
-    X, R = I.workload_inputs(w)
-    n, W = w.n, (w.ell + 63) // 64
-    dev = torch.device("cuda:0")
-    Xd = torch.from_numpy(X).to(dev)
-    Rd = torch.from_numpy(R).to(dev)
-    S = torch.empty((n, W), dtype=torch.int64, device=dev)
-    ctx = msm.Context(0)
-    tau = 2.0 ** -8
-    sub = torch.from_numpy(I.subsample_indices(n, w.subsample, w.seed_sub)).to(dev)
-    star, mstar = msm.bruteforce_eps(ctx, Xd[sub].contiguous(), w.metric, w.eps, cap_hint=1 << 22)
-    insub = torch.zeros(n, dtype=torch.bool, device=dev)
-    insub[sub] = True
-    star_codes = sub[star[:, 0].to(torch.int64)] * n + sub[star[:, 1].to(torch.int64)]
-    rows = I.subsample_indices(n, 20_000, w.seed_sub + 1)
-    per = {}
-    for dt in ("f32", "bf16", "fp8"):
-        def project():
-            if dt == "f32":
-                msm.msm_project(ctx, Xd, Rd, S)
-            else:
-                msm.msm_project_lowp(ctx, Xd, Rd, dt, tau, S)
-
-        project()
-        _, mH = msm.msm_enumerate_pairs(ctx, S, w.ell, w.k, w.h, cap=0)
-        pairs = torch.empty((max(1, int(mH * 1.05) + 1024), 2), dtype=torch.int32, device=dev)
-        verified = torch.empty_like(pairs)
-        for _ in range(args.warmup):
-            project()
-            P, mH = msm.msm_enumerate_pairs(ctx, S, w.ell, w.k, w.h, pairs=pairs)
-            msm.msm_verify(ctx, Xd, P, w.metric, w.eps, out=verified)
-        msm.msm_profile_reset(ctx)
-        msm.msm_profile_enable(ctx, True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            project()
-            P, mH = msm.msm_enumerate_pairs(ctx, S, w.ell, w.k, w.h, pairs=pairs)
-            V, mE = msm.msm_verify(ctx, Xd, P, w.metric, w.eps, out=verified)
-        torch.cuda.synchronize()
-        ms = (time.perf_counter() - t0) * 1e3 / args.steps
-        msm.msm_profile_enable(ctx, False)
-        prof = msm.msm_profile_read(ctx)
-        _, nre = (msm.msm_project_lowp(ctx, Xd, Rd, dt, tau, S, count_recomputed=True) if dt != "f32"
-                  else (None, 0))
-        fr, fr_out = flip_rate(X, R, S, rows)
-        i = V[:, 0].to(torch.int64)
-        j = V[:, 1].to(torch.int64)
-        keep = insub[i] & insub[j]
-        got = torch.unique(i[keep] * n + j[keep])
-        missed = int((~torch.isin(star_codes, got)).sum()) if mstar else 0
-        per[dt] = {"ms_per_step": round(ms, 4), "points_per_s": round(n / (ms / 1e3), 1),
-                   "hamming_pairs": int(mH), "eps_pairs": int(mE),
-                   "flip_rate_vs_fp64": fr, "flip_rate_outside_1e-5_band": fr_out,
-                   "recomputed_fraction": nre / (n * w.ell),
-                   "missing_edge_ratio": (missed / mstar) if mstar else None,
-                   "kernels_ms": {k: round(v[1] / v[0], 4) for k, v in sorted(prof.items())}}
-        log(f"{dt}: {per[dt]}")
-        del pairs, verified
-    out = {"metric": METRIC, "value": per["bf16"]["points_per_s"], "unit": "points/s", "n_gpus": 1,
-           "steps": args.steps, "warmup": args.warmup, "ms_per_step": per["bf16"]["ms_per_step"],
-           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
-           "data": "synthetic sparse lognormal rows",
-           "config": {"workload": w.name, "n": n, "d": w.d, "ell": w.ell, "k": w.k, "h": w.h, "eps": w.eps,
-                      "metric": w.metric, "tau": tau, "reference_subsample": int(sub.numel()),
-                      "reference_true_pairs": int(mstar)},
-           "per_dtype": per}
-    print(json.dumps(out), flush=True)
-    ctx.close()
+def _grow(fn, *args, cap_hint=1 << 20):
+    """Call a pair-producing binding with a buffer grown on capacity errors."""
+    cap = max(1, int(cap_hint))
+    while True:
+        try:
+            return fn(*args, cap=cap)
+        except Exception as e:  # MSMError with the required count
+            if getattr(e, "required", None) is None or getattr(e, "status", 0) != -2:
+                raise
+            cap = int(e.required) + 1
 
 
-def run_mixture(msm, ctx, w, X, Xd, project, steps, warmup, ref_sub=None):
-    """Time `steps` whole steps (project, enumerate, verify) over a mixture
-    workload already on the device, then measure the missing-edge ratio.
-    `project(S)` writes the strings. Returns a dict of results."""
+def run_mixture(msm, ctx, w, Xd, project, steps, warmup, ref_sub=None, Q=1, keep_S=False):
+    """Time `steps` whole steps (project, enumerate, verify) over a workload
+    already on the device, then measure the missing-edge ratio.
+    `project(S)` writes the strings: S is (n, W), or (Q, n, W) for Q pools,
+    enumerated by msm_enumerate_replicates. Returns a dict of results."""
     import torch
 
     n, W = Xd.shape[0], (w.ell + 63) // 64
-    S = torch.empty((n, W), dtype=torch.int64, device=Xd.device)
+    S = torch.empty((Q, n, W) if Q > 1 else (n, W), dtype=torch.int64, device=Xd.device)
+    enum = msm.msm_enumerate_replicates if Q > 1 else msm.msm_enumerate_pairs
 
     # size the output buffers with a count-only pass
     project(S)
-    _, mH = msm.msm_enumerate_pairs(ctx, S, w.ell, w.k, w.h, cap=0)
+    _, mH = enum(ctx, S, w.ell, w.k, w.h, cap=0)
     # groupings the enumeration made (C(k, h), or fewer hierarchical ones)
     C, jblk = msm.msm_enumerate_last_plan(ctx)
     pairs = torch.empty((max(1, int(mH * 1.05) + 1024), 2), dtype=torch.int32, device=Xd.device)
     verified = torch.empty_like(pairs)
-    log(f"hamming pairs {mH}, groupings {C}, j {jblk}")
+    log(f"{w.name} Q={Q}: hamming pairs {mH}, groupings {C}, j {jblk}")
 
     def step():
         project(S)
-        P, m = msm.msm_enumerate_pairs(ctx, S, w.ell, w.k, w.h, pairs=pairs)
+        P, m = enum(ctx, S, w.ell, w.k, w.h, pairs=pairs)
         V, kept = msm.msm_verify(ctx, Xd, P, w.metric, w.eps, out=verified)
         return m, kept
 
@@ -318,22 +283,27 @@ def run_mixture(msm, ctx, w, X, Xd, project, steps, warmup, ref_sub=None):
         phase[name] = {"launches": launches, "avg_ms": total / max(launches, 1), "ms_per_step": total / steps,
                        "timed_region": name == dom}
     t_enum = sum(v["ms_per_step"] for k, v in phase.items()
-                 if k in ("k_part_count", "k_part_scan", "k_part_scatter", "k_bucket", "k_big"))
+                 if k in ("k_part_count", "k_part_scan", "k_part_scatter", "k_bucket", "k_bucket_large", "k_big"))
     missing = missing_edge_ratio(msm, ctx, w, Xd, pairs[:mH], verified[:mE], sub=ref_sub)
-    res = {"ms_per_step": ms_step, "points_per_s": n / (ms_step / 1e3), "combinations": C, "hier_j": jblk,
-           "hamming_pairs": int(mH), "eps_pairs": int(mE), "phase": phase,
+    res = {"ms_per_step": ms_step, "points_per_s": n / (ms_step / 1e3), "steps": steps, "pools": Q,
+           "combinations": C,
+           "hier_j": jblk, "hamming_pairs": int(mH), "eps_pairs": int(mE), "phase": phase,
            "hamming_pairs_per_s_enumerate": (mH / (t_enum / 1e3)) if t_enum else None,
            "eps_pairs_per_s_total": mE / (ms_step / 1e3), "missing_edge_ratio": missing}
-    del pairs, verified, S
+    if keep_S:
+        res["S"] = S
+    del pairs, verified
     return res
 
 
-def roofline_of(res, w, n, W, tag):
+def roofline_of(res, w, n, W, tag, hid=None):
     """Roofline object of the kernel with the most time per step; `tag`
     names the workload variant for the stored traffic measurement."""
     phase = res["phase"]
     dom = max(phase, key=lambda k: phase[k]["ms_per_step"])
-    alg = algorithmic(dom, w, n, res["combinations"], res["hamming_pairs"], res["eps_pairs"], W)
+    per_step = max(1, round(phase[dom]["launches"] / max(res.get("steps", 1), 1)))
+    alg = algorithmic(dom, w, n, res["combinations"], res["hamming_pairs"], res["eps_pairs"], W,
+                      launches=per_step, hid=hid)
     if alg is None:
         return {"kernel": dom, "bound": None, "achieved": None, "peak": None, "unit": None, "frac": None,
                 "traffic": None}
@@ -347,14 +317,114 @@ def roofline_of(res, w, n, W, tag):
             "traffic_unit": "GB per launch", "algorithmic_per_launch": round(amount, 4)}
 
 
-def compact(res):
-    out = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in res.items() if k != "phase"}
-    out["kernels"] = {k: {kk: round(vv, 4) if isinstance(vv, float) else vv for kk, vv in v.items()}
-                      for k, v in sorted(res["phase"].items())}
+def compact(res, full_kernels=True):
+    out = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in res.items() if k not in ("phase", "S")}
+    if full_kernels:
+        out["kernels"] = {k: {kk: round(vv, 4) if isinstance(vv, float) else vv for kk, vv in v.items()}
+                          for k, v in sorted(res["phase"].items())}
+    else:
+        out["kernels_ms_per_step"] = {k: round(v["ms_per_step"], 4) for k, v in sorted(res["phase"].items())}
     return out
 
 
-def run_learned(args):
+def form_summary(res, roof):
+    """The fields every form reports side by side."""
+    mr = res["missing_edge_ratio"]
+    return {"ms_per_step": round(res["ms_per_step"], 4), "points_per_s": round(res["points_per_s"], 1),
+            "pools": res.get("pools", 1), "groupings": res["combinations"],
+            "hamming_pairs": res["hamming_pairs"], "eps_pairs": res["eps_pairs"],
+            "edges_per_s": {"hamming_pairs_per_s_enumerate": round(res["hamming_pairs_per_s_enumerate"] or 0, 1),
+                            "eps_pairs_per_s_total": round(res["eps_pairs_per_s_total"], 1)},
+            "missing_edge_ratio": mr["ratio"], "missing": {k: mr[k] for k in ("subsample", "true_pairs", "missed")},
+            "roofline": roof,
+            "kernels_ms_per_step": {k: round(v["ms_per_step"], 4) for k, v in sorted(res["phase"].items())}}
+
+
+def choose_pools(msm, ctx, w, Xd, Rs, q_max, target):
+    """Least number of string pools Q (each projected by its own R) whose
+    missing-edge ratio on the reference subsample is at most `target`:
+    one untimed pass per Q = 1, 2, ... (Section 4.1, eq. (5); for
+    Euclidean radii on data that are not normalised the bound of Section
+    4.2 does not apply, so Q is measured rather than computed)."""
+    import torch
+
+    n, W = Xd.shape[0], (w.ell + 63) // 64
+    table = []
+    chosen = None
+    for Q in range(1, q_max + 1):
+        S = torch.empty((Q, n, W) if Q > 1 else (n, W), dtype=torch.int64, device=Xd.device)
+        for q in range(Q):
+            msm.msm_project(ctx, Xd, Rs[q], S[q] if Q > 1 else S)
+        P, mH = msm.enumerate_pairs(ctx, S, w.ell, w.k, w.h, cap_hint=1 << 27)
+        V, mE = msm.msm_verify(ctx, Xd, P, w.metric, w.eps)
+        mr = missing_edge_ratio(msm, ctx, w, Xd, P, V)
+        table.append({"Q": Q, "hamming_pairs": int(mH), "eps_pairs": int(mE), "ratio": mr["ratio"],
+                      "missed": mr["missed"], "true_pairs": mr["true_pairs"]})
+        log(f"pools Q={Q}: {table[-1]}")
+        del S, P, V
+        torch.cuda.empty_cache()
+        if mr["ratio"] is not None and mr["ratio"] <= target:
+            chosen = Q
+            break
+    return (chosen or q_max), table
+
+
+def form_precision(args, steps, warmup):
+    """The precision form: 4M sparse cosine rows projected in FP32, BF16 and
+    row-scaled FP8 (FP32 recompute inside |z| < 2^-8 |x|), then the same
+    enumeration and verification; per dtype: flip rate against the FP64
+    projection on sampled rows, recomputed fraction, missing-edge ratio."""
+    import torch
+
+    from paper_0904_3151_amd import inputs as I
+    from paper_0904_3151_amd import msm
+    from paper_0904_3151_amd import params as PR
+
+    w = I.PRECISION
+    log(f"generating {w.name}")
+    X, R = I.workload_inputs(w)
+    n, W = w.n, (w.ell + 63) // 64
+    dev = torch.device("cuda:0")
+    Xd = torch.from_numpy(X).to(dev)
+    Rd = torch.from_numpy(R).to(dev)
+    ctx = msm.Context(0)
+    tau = 2.0 ** -8
+    sub = torch.from_numpy(I.subsample_indices(n, w.subsample, w.seed_sub)).to(dev)
+    rows = I.subsample_indices(n, 20_000, w.seed_sub + 1)
+    per = {}
+    for dt in ("f32", "bf16", "fp8"):
+        def project(S, dt=dt):
+            if dt == "f32":
+                msm.msm_project(ctx, Xd, Rd, S)
+            else:
+                msm.msm_project_lowp(ctx, Xd, Rd, dt, tau, S)
+
+        res = run_mixture(msm, ctx, w, Xd, project, steps, warmup, ref_sub=sub, keep_S=True)
+        fr, fr_out = flip_rate(X, R, res["S"], rows)
+        nre = msm.msm_project_lowp(ctx, Xd, Rd, dt, tau, res["S"], count_recomputed=True)[1] if dt != "f32" else 0
+        per[dt] = form_summary(res, roofline_of(res, w, n, W, f"{w.name}:{dt}"))
+        per[dt].update({"flip_rate_vs_fp64": fr, "flip_rate_outside_1e-5_band": fr_out,
+                        "recomputed_fraction": nre / (n * w.ell)})
+        log(f"precision {dt}: {per[dt]}")
+        del res
+        torch.cuda.empty_cache()
+    p = PR.flip_probability(w.eps)
+    out = {"config": {"workload": w.name, "n": n, "d": w.d, "ell": w.ell, "k": w.k, "h": w.h, "eps": w.eps,
+                      "metric": w.metric, "tau": tau, "reference_subsample": int(sub.numel())},
+           "per_dtype": per,
+           "bound_section_4_2": {"p": p, "miss_per_pool": PR.miss_probability(w.ell, w.h, p),
+                                 "pools_for_1e-3": PR.replicates_needed(w.ell, w.h, p, 1e-3)},
+           "note": ("at ell = 240 and h = 8 the Hamming threshold lies far below the angle that cosine "
+                    "eps = 0.2 allows, so nearly every epsilon-pair is missed whatever the projection's "
+                    "precision; no number of pools within reach meets 1e-3 (the bound above), and the form "
+                    "compares the precisions' flip rates and speed")}
+    ctx.close()
+    del Xd, Rd, X
+    torch.cuda.empty_cache()
+    return out
+
+
+def form_learned(args, steps, warmup):
     """The learned-projection form: 2M mixture points (cluster radius reading
     of sigma), a 128-512-128 network trained on the GPU on epsilon-pairs and
     non-pairs mined by the exhaustive search from a 100k-point sample, then
@@ -374,6 +444,7 @@ def run_learned(args):
     dev = torch.device("cuda:0")
     Xd = torch.from_numpy(X).to(dev)
     Rd = torch.from_numpy(R).to(dev)
+    del X
     ctx = msm.Context(0)
     train_idx = I.subsample_indices(n, 100_000, w.seed_sub + 7)
     held = np.setdiff1d(np.arange(n, dtype=np.int64), train_idx)
@@ -393,36 +464,127 @@ def run_learned(args):
     t_train = time.perf_counter() - t0
     log(f"mined {stats} in {t_mine:.1f} s; trained {nsteps - 1} steps in {t_train:.1f} s, "
         f"loss {losses[0]:.3f} -> {np.mean(losses[-20:]):.3f}")
-
-    learned = run_mixture(msm, ctx, w, X, Xd, lambda S: msm.msm_project_mlp(ctx, Xd, params, cfg.hid, w.ell, S),
-                          args.steps, args.warmup, ref_sub)
-    log(f"learned: {compact(learned)}")
-    rand = run_mixture(msm, ctx, w, X, Xd, lambda S: msm.msm_project(ctx, Xd, Rd, S), args.steps, args.warmup,
-                       ref_sub)
-    log(f"random: {compact(rand)}")
-    flops = 2.0 * n * (w.d * cfg.hid + cfg.hid * w.ell)
+    learned = run_mixture(msm, ctx, w, Xd, lambda S: msm.msm_project_mlp(ctx, Xd, params, cfg.hid, w.ell, S),
+                          steps, warmup, ref_sub)
+    rand = run_mixture(msm, ctx, w, Xd, lambda S: msm.msm_project(ctx, Xd, Rd, S), steps, warmup, ref_sub)
     ph = learned["phase"].get("k_mlp_fused")
     mlp_roof = None
     if ph:
-        ach = flops / (ph["avg_ms"] / 1e3) / 1e12
+        amount, unit, _ = algorithmic("k_mlp_fused", w, n, 0, 0, 0, W, hid=cfg.hid)
+        ach = amount / (ph["avg_ms"] / 1e3)
         mlp_roof = {"kernel": "k_mlp_fused", "bound": "mfma", "achieved": round(ach, 2),
-                    "peak": BF16_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(ach / BF16_MFMA_PEAK_TFLOPS, 4),
+                    "peak": BF16_MFMA_PEAK_TFLOPS, "unit": unit, "frac": round(ach / BF16_MFMA_PEAK_TFLOPS, 4),
                     "traffic": None}
-    out = {"metric": METRIC, "value": round(learned["points_per_s"], 1), "unit": "points/s", "n_gpus": 1,
-           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(learned["ms_per_step"], 4),
-           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
-           "data": "synthetic Gaussian mixture, sigma_mode=radius",
-           "config": {"workload": w.name, "n": n, "d": w.d, "ell": w.ell, "k": w.k, "h": w.h, "eps": w.eps,
+    out = {"config": {"workload": w.name, "n": n, "d": w.d, "ell": w.ell, "k": w.k, "h": w.h, "eps": w.eps,
                       "metric": w.metric, "hidden": cfg.hid, "train_sample": int(train_idx.size),
-                      "reference_subsample": int(ref_sub.numel())},
+                      "reference_subsample": int(ref_sub.numel()), "sigma_mode": "radius"},
            "training": {"mining": stats, "mining_s": round(t_mine, 2), "steps": nsteps - 1,
                         "train_s": round(t_train, 2), "loss_first": losses[0],
                         "loss_last20": float(np.mean(losses[-20:])), "config": vars(cfg)},
-           "learned": compact(learned), "random_lsh": compact(rand),
-           "roofline": roofline_of(learned, w, n, W, f"{w.name}:radius:learned"), "roofline_projection": mlp_roof,
-           "cpu_baseline": None}
-    print(json.dumps(out), flush=True)
+           "learned": form_summary(learned, roofline_of(learned, w, n, W, f"{w.name}:radius:learned")),
+           "random_lsh": form_summary(rand, roofline_of(rand, w, n, W, f"{w.name}:radius")),
+           "roofline_projection": mlp_roof}
     ctx.close()
+    del Xd, Rd, Xt
+    torch.cuda.empty_cache()
+    return out
+
+
+def form_sweep(args, steps, warmup, cpu_n=0):
+    """Output sensitivity (Sections 2.3 and 5.4): whole steps on the
+    paper-scale mixture (radius reading, 5000 clusters) at n = 125k ... 2M,
+    with time per 10k output pairs and the dominant kernel's roofline at
+    each n, the oracle's step at the smallest n on the host, and the worst
+    case of Section 2.3 where all strings are identical and every pair is
+    output."""
+    import torch
+
+    from paper_0904_3151_amd import inputs as I
+    from paper_0904_3151_amd import msm
+
+    w0 = I.PAPER_SCALE
+    dev = torch.device("cuda:0")
+    ctx = msm.Context(0)
+    R = I.projection_matrix(w0.d, w0.ell, w0.seed_r)
+    Rd = torch.from_numpy(R).to(dev)
+    rows = []
+    cpu = None
+    for n in (125_000, 250_000, 500_000, 1_000_000, 2_000_000):
+        X, _ = I.gaussian_mixture(n, w0.d, w0.n_centres, w0.sigma, w0.seed_data, "radius")
+        w = I.Workload(f"sweep-mixture-n{n}", n, w0.d, w0.ell, w0.k, w0.h, w0.eps, w0.metric, w0.n_centres,
+                       w0.sigma, w0.seed_data, w0.seed_r, w0.seed_sub, subsample=min(n, 50_000))
+        Xd = torch.from_numpy(X).to(dev)
+        res = run_mixture(msm, ctx, w, Xd, lambda S: msm.msm_project(ctx, Xd, Rd, S), steps, warmup)
+        roof = roofline_of(res, w, n, 2, f"{w.name}:radius")
+        mr = res["missing_edge_ratio"]
+        rows.append({"n": n, "ms_per_step": round(res["ms_per_step"], 4), "points_per_s": round(res["points_per_s"], 1),
+                     "hamming_pairs": res["hamming_pairs"], "eps_pairs": res["eps_pairs"],
+                     "ms_per_10k_eps_pairs": round(res["ms_per_step"] / max(res["eps_pairs"], 1) * 1e4, 6),
+                     "missing_edge_ratio": mr["ratio"], "groupings": res["combinations"],
+                     "dominant": roof["kernel"], "dominant_frac": roof["frac"], "dominant_unit": roof["unit"]})
+        log(rows[-1])
+        if cpu_n and n == 125_000:
+            cpu = cpu_baseline(w, X, [R], n)
+            cpu["sample"] = f"n = {n} of the sweep, " + cpu["sample"]
+        del Xd, X, res
+        torch.cuda.empty_cache()
+    # worst case: n identical strings, all n (n - 1) / 2 pairs are output
+    n = 20_000
+    S = torch.zeros((n, 2), dtype=torch.int64, device=dev)
+    _, m = msm.msm_enumerate_pairs(ctx, S, w0.ell, w0.k, w0.h, cap=0)
+    pairs = torch.empty((m, 2), dtype=torch.int32, device=dev)
+    msm.msm_enumerate_pairs(ctx, S, w0.ell, w0.k, w0.h, pairs=pairs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        msm.msm_enumerate_pairs(ctx, S, w0.ell, w0.k, w0.h, pairs=pairs)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    worst = {"n": n, "pairs": int(m), "expected": n * (n - 1) // 2, "ms": round(ms, 3),
+             "pairs_per_s": round(m / ms * 1e3, 1),
+             "write_GB_per_s": round(m * 8 / (ms / 1e3) / 1e9, 1)}
+    log(worst)
+    ratios = [round(rows[i + 1]["ms_per_step"] / rows[i]["ms_per_step"], 3) for i in range(len(rows) - 1)]
+    pair_ratios = [round(rows[i + 1]["eps_pairs"] / max(rows[i]["eps_pairs"], 1), 3) for i in range(len(rows) - 1)]
+    ctx.close()
+    return {"config": {"workload": "sweep-mixture-d128-l128-k8-h4-radius", "k": w0.k, "h": w0.h, "ell": w0.ell,
+                       "eps": w0.eps},
+            "sweep": rows, "time_ratio_when_n_doubles": ratios, "eps_pairs_ratio_when_n_doubles": pair_ratios,
+            "all_identical": worst, "cpu_baseline": cpu}
+
+
+def line(metric_value, ms, args, dtype, data, config, **extra):
+    out = {"metric": METRIC, "value": round(metric_value, 1), "unit": "points/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": dtype, "data": data, "config": config}
+    out.update(extra)
+    return out
+
+
+def run_precision(args):
+    f = form_precision(args, args.steps, args.warmup)
+    bf = f["per_dtype"]["bf16"]
+    print(json.dumps(line(bf["points_per_s"], bf["ms_per_step"], args, "bf16", "synthetic sparse lognormal rows",
+                          f["config"], **{k: v for k, v in f.items() if k != "config"},
+                          roofline=bf["roofline"], cpu_baseline=None)), flush=True)
+
+
+def run_learned(args):
+    f = form_learned(args, args.steps, args.warmup)
+    le = f["learned"]
+    print(json.dumps(line(le["points_per_s"], le["ms_per_step"], args, "bf16",
+                          "synthetic Gaussian mixture, sigma_mode=radius", f["config"],
+                          **{k: v for k, v in f.items() if k != "config"}, roofline=le["roofline"],
+                          cpu_baseline=None)), flush=True)
+
+
+def run_sweep(args):
+    f = form_sweep(args, args.steps, args.warmup, cpu_n=0 if args.no_cpu_baseline else 1)
+    last = f["sweep"][-2]
+    print(json.dumps(line(last["points_per_s"], last["ms_per_step"], args, "f32",
+                          "synthetic Gaussian mixture, sigma_mode=radius", f["config"],
+                          **{k: v for k, v in f.items() if k not in ("config", "cpu_baseline")},
+                          roofline=None, cpu_baseline=f["cpu_baseline"])), flush=True)
 
 
 def run_batched(args):
@@ -518,71 +680,96 @@ def run_batched(args):
     ctx.close()
 
 
-def run_sweep(args):
-    """Output sensitivity (Sections 2.3 and 5.4): whole steps on the
-    paper-scale mixture (radius reading, 5000 clusters) at n = 125k ... 2M,
-    with time per 10k output pairs, and the worst case of Section 2.3 where
-    all strings are identical and every pair is output."""
-    import numpy as np
+
+
+def run_paper(args):
+    """The default line: the headline step (radius reading, Q pools chosen
+    for a missing-edge ratio of at most 1e-3) and the other forms."""
     import torch
 
     from paper_0904_3151_amd import inputs as I
     from paper_0904_3151_amd import msm
 
     w = I.PAPER_SCALE
+    target = 1e-3
+    log(f"generating {w.name} (radius)")
+    X, _ = I.workload_inputs(w, sigma_mode="radius")
+    n, W = w.n, (w.ell + 63) // 64
     dev = torch.device("cuda:0")
+    Xd = torch.from_numpy(X).to(dev)
+    Rs_np = I.projection_matrices(w.d, w.ell, args.q_max, w.seed_r)
+    Rs = [torch.from_numpy(Rs_np[q]).to(dev) for q in range(args.q_max)]
     ctx = msm.Context(0)
-    R = torch.from_numpy(I.projection_matrix(w.d, w.ell, w.seed_r)).to(dev)
-    rows = []
-    for n in (125_000, 250_000, 500_000, 1_000_000, 2_000_000):
-        X, _ = I.gaussian_mixture(n, w.d, w.n_centres, w.sigma, w.seed_data, "radius")
-        Xd = torch.from_numpy(X).to(dev)
-        del X
-        S = torch.empty((n, 2), dtype=torch.int64, device=dev)
-        msm.msm_project(ctx, Xd, R, S)
-        _, mH = msm.msm_enumerate_pairs(ctx, S, w.ell, w.k, w.h, cap=0)
-        pairs = torch.empty((int(mH * 1.05) + 1024, 2), dtype=torch.int32, device=dev)
-        out = torch.empty_like(pairs)
-        for _ in range(args.warmup):
-            msm.msm_project(ctx, Xd, R, S)
-            P, mH = msm.msm_enumerate_pairs(ctx, S, w.ell, w.k, w.h, pairs=pairs)
-            msm.msm_verify(ctx, Xd, P, w.metric, w.eps, out=out)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            msm.msm_project(ctx, Xd, R, S)
-            P, mH = msm.msm_enumerate_pairs(ctx, S, w.ell, w.k, w.h, pairs=pairs)
-            _, mE = msm.msm_verify(ctx, Xd, P, w.metric, w.eps, out=out)
-        torch.cuda.synchronize()
-        ms = (time.perf_counter() - t0) * 1e3 / args.steps
-        rows.append({"n": n, "ms_per_step": round(ms, 4), "hamming_pairs": int(mH), "eps_pairs": int(mE),
-                     "ms_per_10k_pairs": round(ms / max(mE, 1) * 1e4, 6), "points_per_s": round(n / ms * 1e3, 1)})
-        log(rows[-1])
-        del Xd, S, pairs, out, P
+    Q, q_table = choose_pools(msm, ctx, w, Xd, Rs, args.q_max, target)
+
+    def project_pools(S, Q=Q):
+        if Q == 1:
+            msm.msm_project(ctx, Xd, Rs[0], S)
+        else:
+            for q in range(Q):
+                msm.msm_project(ctx, Xd, Rs[q], S[q])
+
+    res = run_mixture(msm, ctx, w, Xd, project_pools, args.steps, args.warmup, Q=Q)
+    tag = f"{w.name}:radius" + (f":q{Q}" if Q > 1 else "")
+    roof = roofline_of(res, w, n, W, tag)
+    forms = {}
+    errors = {}
+
+    def attempt(name, fn):
+        try:
+            forms[name] = fn()
+        except Exception as e:  # a form that fails is reported, the headline stands
+            errors[name] = f"{type(e).__name__}: {e}"
+            log(f"form {name} failed: {errors[name]}")
         torch.cuda.empty_cache()
-    # worst case: n identical strings, all n (n - 1) / 2 pairs are output
-    n = 20_000
-    S = torch.zeros((n, 2), dtype=torch.int64, device=dev)
-    _, m = msm.msm_enumerate_pairs(ctx, S, w.ell, w.k, w.h, cap=0)
-    pairs = torch.empty((m, 2), dtype=torch.int32, device=dev)
-    msm.msm_enumerate_pairs(ctx, S, w.ell, w.k, w.h, pairs=pairs)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        msm.msm_enumerate_pairs(ctx, S, w.ell, w.k, w.h, pairs=pairs)
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3 / args.steps
-    worst = {"n": n, "pairs": int(m), "expected": n * (n - 1) // 2, "ms": round(ms, 3),
-             "pairs_per_s": round(m / ms * 1e3, 1)}
-    log(worst)
-    ratios = [round(rows[i + 1]["ms_per_step"] / rows[i]["ms_per_step"], 3) for i in range(len(rows) - 1)]
-    last = rows[-2]
-    out = {"metric": METRIC, "value": last["points_per_s"], "unit": "points/s", "n_gpus": 1, "steps": args.steps,
-           "warmup": args.warmup, "ms_per_step": last["ms_per_step"], "higher_is_better": True, "scaling": "weak",
-           "vs_baseline": None, "dtype": "f32", "data": "synthetic Gaussian mixture, sigma_mode=radius",
-           "config": {"workload": "sweep-mixture-d128-l128-k8-h4-radius", "k": w.k, "h": w.h, "ell": w.ell},
-           "sweep": rows, "time_ratio_when_n_doubles": ratios, "all_identical": worst,
-           "roofline": None, "cpu_baseline": None}
+
+    small = max(1, min(args.steps, 5))
+    if not args.headline_only:
+        def single_pool():
+            r1 = run_mixture(msm, ctx, w, Xd, lambda S: msm.msm_project(ctx, Xd, Rs[0], S), small,
+                             min(args.warmup, 2))
+            return form_summary(r1, roofline_of(r1, w, n, W, f"{w.name}:radius"))
+
+        if Q > 1:
+            attempt("single_pool_radius", single_pool)
+
+        def coord():
+            Xc, _ = I.workload_inputs(w, sigma_mode="coord")
+            Xcd = torch.from_numpy(Xc).to(dev)
+            del Xc
+            rc = run_mixture(msm, ctx, w, Xcd, lambda S: msm.msm_project(ctx, Xcd, Rs[0], S), small,
+                             min(args.warmup, 2))
+            out = form_summary(rc, roofline_of(rc, w, n, W, f"{w.name}:coord"))
+            out["note"] = "per-coordinate reading of sigma: no pair lies within eps, the ratio is undefined"
+            return out
+
+        attempt("coord_reading", coord)
+    cpu = None
+    if not args.no_cpu_baseline:
+        sample = args.cpu_sample if 0 < args.cpu_sample < n else n
+        log(f"cpu baseline on {sample} points, {Q} pool(s)")
+        cpu = cpu_baseline(w, X, Rs_np, sample, Q=Q)
+    del X
+    if not args.headline_only:
+        attempt("learned", lambda: form_learned(args, small, min(args.warmup, 2)))
+        attempt("precision", lambda: form_precision(args, small, min(args.warmup, 2)))
+        attempt("sweep", lambda: form_sweep(args, small, min(args.warmup, 2)))
+
+    c = compact(res)
+    mr = res["missing_edge_ratio"]
+    mr["target"] = target
+    out = line(res["points_per_s"], res["ms_per_step"], args, "f32",
+               "synthetic Gaussian mixture, sigma_mode=radius",
+               {"workload": w.name, "n": n, "d": w.d, "ell": w.ell, "k": w.k, "h": w.h, "eps": w.eps,
+                "metric": w.metric, "sigma_mode": "radius", "pools": Q, "groupings": res["combinations"],
+                "hier_j": res["hier_j"],
+                "projection_arith": ("fp32 as three bf16 parts, six products, fp32 accumulation"
+                                     if w.ell <= 128 and w.d <= 256 else "fp32 products")},
+               edges_per_s={"hamming_pairs_per_s_enumerate": c["hamming_pairs_per_s_enumerate"],
+                            "eps_pairs_per_s_total": c["eps_pairs_per_s_total"]},
+               counts={"hamming_pairs": res["hamming_pairs"], "eps_pairs": res["eps_pairs"]},
+               kernels=c["kernels"], missing_edge_ratio=mr, pools_search=q_table, roofline=roof,
+               cpu_baseline=cpu, forms=forms, form_errors=errors or None)
     print(json.dumps(out), flush=True)
     ctx.close()
 
@@ -592,19 +779,20 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--sigma-mode", default="coord", choices=["coord", "radius"])
-    ap.add_argument("--cpu-sample", type=int, default=0, help="rows for the CPU oracle (0: all)")
+    ap.add_argument("--cpu-sample", type=int, default=500_000,
+                    help="rows for the CPU oracle (0: all); the default keeps the oracle's step near 10 s")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-second-reading", action="store_true",
-                    help="skip the run under the other reading of sigma")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the headline step (no other forms in the line)")
+    ap.add_argument("--q-max", type=int, default=6, help="most string pools the headline may use")
     ap.add_argument("--epochs", type=int, default=20, help="training epochs of the learned form")
     ap.add_argument("--train-h", type=int, default=0,
                     help="h of the training loss of the learned form (0: twice the workload's h)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES on the device a few times (reference for the HBM counters)")
     ap.add_argument("--workload", default="paper", choices=["paper", "precision", "learned", "batched", "sweep"],
-                    help="paper: the 1M mixture (default); precision: 4M sparse rows, FP32/BF16/FP8; "
-                         "learned: 2M mixture, trained network vs random projection; "
+                    help="paper: the 1M mixture with every form (default); precision: 4M sparse rows, "
+                         "FP32/BF16/FP8; learned: 2M mixture, trained network vs random projection; "
                          "batched: 512 instances in one captured graph; "
                          "sweep: n from 125k to 2M and the all-identical worst case")
     args = ap.parse_args()
@@ -616,85 +804,8 @@ def main():
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
         return
-    if args.workload == "precision":
-        run_precision(args)
-        return
-    if args.workload == "learned":
-        run_learned(args)
-        return
-    if args.workload == "batched":
-        run_batched(args)
-        return
-    if args.workload == "sweep":
-        run_sweep(args)
-        return
-
-    import torch
-
-    from paper_0904_3151_amd import inputs as I
-    from paper_0904_3151_amd import msm
-
-    w = I.PAPER_SCALE
-    log(f"generating {w.name} ({args.sigma_mode})")
-    X, R = I.workload_inputs(w, sigma_mode=args.sigma_mode)
-    n, W = w.n, (w.ell + 63) // 64
-    dev = torch.device("cuda:0")
-    Xd = torch.from_numpy(X).to(dev)
-    Rd = torch.from_numpy(R).to(dev)
-    ctx = msm.Context(0)
-    res = run_mixture(msm, ctx, w, X, Xd, lambda S: msm.msm_project(ctx, Xd, Rd, S), args.steps, args.warmup)
-    roof = roofline_of(res, w, n, W, f"{w.name}:{args.sigma_mode}")
-    second = None
-    if not args.no_second_reading:
-        other = "radius" if args.sigma_mode == "coord" else "coord"
-        log(f"generating {w.name} ({other})")
-        X2, _ = I.workload_inputs(w, sigma_mode=other)
-        X2d = torch.from_numpy(X2).to(dev)
-        del X2
-        r2 = run_mixture(msm, ctx, w, None, X2d, lambda S: msm.msm_project(ctx, X2d, Rd, S), args.steps,
-                         args.warmup)
-        second = compact(r2)
-        second["sigma_mode"] = other
-        second["roofline"] = roofline_of(r2, w, n, W, f"{w.name}:{other}")
-        del X2d
-        torch.cuda.empty_cache()
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        sample = args.cpu_sample if 0 < args.cpu_sample < n else n
-        log(f"cpu baseline on {sample} points")
-        cpu = cpu_baseline(w, X, R, sample)
-
-    c = compact(res)
-    out = {
-        "metric": METRIC,
-        "value": round(res["points_per_s"], 1),
-        "unit": "points/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(res["ms_per_step"], 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": f"synthetic Gaussian mixture, sigma_mode={args.sigma_mode}",
-        "config": {"workload": w.name, "n": n, "d": w.d, "ell": w.ell, "k": w.k, "h": w.h, "eps": w.eps,
-                   "metric": w.metric, "groupings": res["combinations"], "hier_j": res["hier_j"],
-                   "sigma_mode": args.sigma_mode,
-                   "projection_arith": ("fp32 as three bf16 parts, six products, fp32 accumulation"
-                                        if w.ell <= 128 and w.d <= 256 else "fp32 products")},
-        "edges_per_s": {"hamming_pairs_per_s_enumerate": c["hamming_pairs_per_s_enumerate"],
-                        "eps_pairs_per_s_total": c["eps_pairs_per_s_total"]},
-        "counts": {"hamming_pairs": res["hamming_pairs"], "eps_pairs": res["eps_pairs"]},
-        "kernels": c["kernels"],
-        "missing_edge_ratio": res["missing_edge_ratio"],
-        "roofline": roof,
-        "second_reading": second,
-        "cpu_baseline": cpu,
-    }
-    print(json.dumps(out), flush=True)
-    ctx.close()
+    {"paper": run_paper, "precision": run_precision, "learned": run_learned, "batched": run_batched,
+     "sweep": run_sweep}[args.workload](args)
 
 
 if __name__ == "__main__":
