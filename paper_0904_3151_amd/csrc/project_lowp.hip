@@ -76,13 +76,16 @@ __global__ void k_lp_zero(unsigned long long* c)
 }
 
 // Column scales of R: ib[c] = 240 / max_t |R_tc| (1 for a zero column).
+// One wave per column: lanes stride over t, then a shuffle maximum.
 __global__ void k_lp_col_scale(const float* __restrict__ R, int d, int ell, float* __restrict__ ib)
 {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= ell) return;
+    const int c = blockIdx.x;
+    const int lane = threadIdx.x;
     float m = 0.f;
-    for (int t = 0; t < d; ++t) m = fmaxf(m, fabsf(R[(int64_t)t * ell + c]));
-    ib[c] = m > 0.f ? FP8_MAX / m : 1.0f;
+    for (int t = lane; t < d; t += 64) m = fmaxf(m, fabsf(R[(int64_t)t * ell + c]));
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+    if (lane == 0) ib[c] = m > 0.f ? FP8_MAX / m : 1.0f;
 }
 
 // R transposed to ell x d (FP32) for the margin recompute.
@@ -389,6 +392,199 @@ __global__ __launch_bounds__(LP_THREADS) void k_project_lp(
     }
 }
 
+// Recomputes the queued margin entries of one wave (rows of at most 256
+// aligned floats) as FP32 dot products of a row of X and a row of R^T:
+// eight teams of eight lanes, each lane with four 16-byte pieces of both
+// rows in flight at a time, then a shuffle sum inside the team. A positive
+// result sets the entry's bit in the wave's LDS copy of its output words.
+// Called by the whole wave.
+__device__ __forceinline__ void recompute_queue8(const float* __restrict__ X, int64_t ldx, int d,
+                                                 const float* __restrict__ Rt, int64_t row0, const uint32_t* q,
+                                                 uint32_t& qn, unsigned long long* words)
+{
+    const int lane = __lane_id();
+    const int team = lane >> 3, tl = lane & 7;
+    const uint32_t cnt = qn;
+    for (uint32_t q0 = 0; q0 < cnt; q0 += 8) {
+        const uint32_t qi = q0 + team;
+        const bool ok = qi < cnt;
+        const uint32_t e = ok ? q[qi] : 0u;
+        const int rr = (int)(e >> 8), c = (int)(e & 0xFF);
+        const float* xg = X + (row0 + rr) * ldx;
+        const float* rg = Rt + (int64_t)c * d;
+        float z = 0.f;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {  // two halves of four pieces, all loads of a half in flight
+            floatx4 a[4], b[4];
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const int t = 4 * tl + 32 * (4 * h + s);
+                const bool in = ok && t < d;
+                a[s] = in ? *reinterpret_cast<const floatx4*>(xg + t) : floatx4{0.f, 0.f, 0.f, 0.f};
+                b[s] = in ? *reinterpret_cast<const floatx4*>(rg + t) : floatx4{0.f, 0.f, 0.f, 0.f};
+            }
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                z = fmaf(a[s][0], b[s][0], z);
+                z = fmaf(a[s][1], b[s][1], z);
+                z = fmaf(a[s][2], b[s][2], z);
+                z = fmaf(a[s][3], b[s][3], z);
+            }
+        }
+#pragma unroll
+        for (int o = 4; o > 0; o >>= 1) z += __shfl_xor(z, o, 64);
+        if (ok && tl == 0 && z > 0.f) atomicOr(&words[rr * 4 + (c >> 6)], 1ull << (c & 63));
+    }
+    qn = 0;
+}
+
+// Rows of at most 256 floats with 16-byte alignment: all of R's operand
+// copy stays in LDS for the whole launch (at most 128 KB for BF16), one
+// persistent workgroup of LPR_THREADS per CU (two for FP8), and each wave
+// requests its next 16 rows as soon as the current rows' products are
+// issued, so their loads overlap the epilogue and the margin recompute.
+constexpr int LPR_THREADS = 512;
+constexpr int LPR_WAVES = LPR_THREADS / 64;
+constexpr int LPR_RQ = 512;  // recompute queue entries per wave
+
+template <int DT, int NCB>
+__global__ __launch_bounds__(LPR_THREADS) void k_project_lp_res(
+    const float* __restrict__ X, int64_t n, int d, int64_t ldx, const float* __restrict__ Rt, int ell,
+    const typename BOp<DT>::T* __restrict__ Rp, const float* __restrict__ ib, uint64_t* __restrict__ S, int W,
+    int nkc, float tau, unsigned long long* recomputed)
+{
+    typedef typename BOp<DT>::T BT;
+    extern __shared__ __attribute__((aligned(16))) char lds_raw[];
+    BT* Bl = reinterpret_cast<BT*>(lds_raw);  // [nkc][NCB][64]
+    __shared__ uint32_t rq[LPR_WAVES][LPR_RQ];
+    __shared__ unsigned long long wordsL[LPR_WAVES][16 * 4];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int g = lane >> 4;
+    const int r16 = lane & 15;
+    constexpr int ROWS_PER_TILE = LPR_WAVES * 16;
+    const int64_t ntiles = (n + ROWS_PER_TILE - 1) / ROWS_PER_TILE;
+    {
+        const int cnt = nkc * NCB * 64;
+        for (int e = threadIdx.x; e < cnt; e += LPR_THREADS) Bl[e] = Rp[e];
+    }
+    __syncthreads();
+    float ibc[NCB];
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) {
+        const int c = cb * 16 + r16;
+        ibc[cb] = (DT == MSM_FP8_E4M3 && c < ell) ? ib[c] : 1.0f;
+    }
+    // the lane's slice of its row: k = 32 kc + 8 g + i
+    float xv[LP_KREG_CHUNKS][8];
+    auto load_rows = [&](int64_t tile) {
+        const int64_t row = tile * ROWS_PER_TILE + (int64_t)wave * 16 + r16;
+        const bool rv = tile < ntiles && row < n;
+        const float* xr = X + (rv ? row : 0) * ldx;
+#pragma unroll
+        for (int kc = 0; kc < LP_KREG_CHUNKS; ++kc) {
+            const int kb = kc * 32 + 8 * g;
+            const bool in = rv && kc < nkc && kb < d;  // d % 4 == 0: kb < d covers kb .. kb + 3
+            const floatx4 u0 = in ? *reinterpret_cast<const floatx4*>(xr + kb) : floatx4{0.f, 0.f, 0.f, 0.f};
+            const floatx4 u1 =
+                (in && kb + 4 < d) ? *reinterpret_cast<const floatx4*>(xr + kb + 4) : floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                xv[kc][i] = u0[i];
+                xv[kc][4 + i] = u1[i];
+            }
+        }
+    };
+    int64_t tile = blockIdx.x;
+    load_rows(tile);
+    for (; tile < ntiles; tile += gridDim.x) {
+        const int64_t row0 = tile * ROWS_PER_TILE + (int64_t)wave * 16;
+        float nrm2 = 0.f, mx = 0.f;
+#pragma unroll
+        for (int kc = 0; kc < LP_KREG_CHUNKS; ++kc)
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                nrm2 = fmaf(xv[kc][i], xv[kc][i], nrm2);
+                mx = fmaxf(mx, fabsf(xv[kc][i]));
+            }
+        nrm2 += __shfl_xor(nrm2, 16, 64);
+        nrm2 += __shfl_xor(nrm2, 32, 64);
+        mx = fmaxf(mx, __shfl_xor(mx, 16, 64));
+        mx = fmaxf(mx, __shfl_xor(mx, 32, 64));
+        const float ia = (DT == MSM_FP8_E4M3 && mx > 0.f) ? FP8_MAX / mx : 1.0f;
+        floatx4 acc[NCB];
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) acc[cb] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kc = 0; kc < LP_KREG_CHUNKS; ++kc) {
+            if (kc < nkc) {
+                const BT a = pack8<DT>(xv[kc], ia);
+#pragma unroll
+                for (int cb = 0; cb < NCB; ++cb) acc[cb] = mfma<DT>(a, Bl[(kc * NCB + cb) * 64 + lane], acc[cb]);
+            }
+        }
+        // the next rows' loads go out before this tile's epilogue
+        load_rows(tile + gridDim.x);
+
+        // Epilogue as in k_project_lp: signs by ballot, margin entries
+        // (|z| < tau ||x|| in scaled units) queued for the FP32 recompute.
+        float thr[4];
+        bool rowok[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int rr = 4 * g + i;
+            const float nr2 = __shfl(nrm2, rr, 64);
+            const float iar = __shfl(ia, rr, 64);
+            thr[i] = tau * sqrtf(nr2) * iar;
+            rowok[i] = row0 + rr < n;
+        }
+        const int orow = lane & 15, oword = lane >> 4;
+        uint64_t word = 0;
+        uint32_t qn = 0;  // wave-uniform queue length
+        unsigned long long nre = 0;
+        bool queued = false;
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) {
+            const int c = cb * 16 + r16;
+            const bool colok = c < ell;
+            uint64_t m[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float zt = acc[cb][i];
+                const uint64_t pos = __ballot(zt > 0.f);
+                const uint64_t mar = __ballot(rowok[i] && colok && fabsf(zt) < thr[i] * ibc[cb]);
+                m[i] = pos & ~mar;
+                if (mar) {
+                    queued = true;
+                    if ((mar >> lane) & 1ull) {
+                        const uint32_t q = qn + (uint32_t)__popcll(mar & msm::lanemask_lt());
+                        rq[wave][q] = ((uint32_t)(4 * g + i) << 8) | (uint32_t)c;
+                    }
+                    qn += (uint32_t)__popcll(mar);
+                }
+            }
+            const uint64_t mi = m[orow & 3];
+            const uint64_t bits = (mi >> (16 * (orow >> 2))) & 0xFFFFull;
+            if ((cb >> 2) == oword) word |= bits << (16 * (cb & 3));
+            if (qn > LPR_RQ - 4 * 64) {  // flush before the queue can overflow
+                wordsL[wave][orow * 4 + oword] = word;
+                nre += qn;
+                recompute_queue8(X, ldx, d, Rt, row0, rq[wave], qn, wordsL[wave]);
+                word = wordsL[wave][orow * 4 + oword];
+            }
+        }
+        if (queued) {
+            wordsL[wave][orow * 4 + oword] = word;
+            nre += qn;
+            recompute_queue8(X, ldx, d, Rt, row0, rq[wave], qn, wordsL[wave]);
+            word = wordsL[wave][orow * 4 + oword];
+        }
+        const int64_t grow = row0 + orow;
+        if (grow < n && oword < W) S[grow * W + oword] = word;
+        if (recomputed && lane == 0 && nre) atomicAdd(recomputed, nre);
+    }
+}
+
 template <int DT, int NCB>
 msm_status launch_lp(msm_ctx* ctx, const float* X, int64_t n, int d, int64_t ldx, const float* R, int ell,
                      float tau, uint64_t* S, int64_t* n_recomputed, hipStream_t stream)
@@ -417,16 +613,29 @@ msm_status launch_lp(msm_ctx* ctx, const float* X, int64_t n, int d, int64_t ldx
     {
         msm::KernelTimer kt(ctx, stream, "k_lp_prep_r");
         if (DT == MSM_FP8_E4M3)
-            hipLaunchKernelGGL(k_lp_col_scale, dim3((ell + 63) / 64), dim3(64), 0, stream, R, d, ell, ib);
+            hipLaunchKernelGGL(k_lp_col_scale, dim3(ell), dim3(64), 0, stream, R, d, ell, ib);
         const int ne = nkc * NCB * 64;
         hipLaunchKernelGGL((k_lp_prep_r<DT>), dim3((ne + 255) / 256), dim3(256), 0, stream, R, d, ell, NCB, nkc,
                            (const float*)ib, Rp);
         hipLaunchKernelGGL(k_lp_transpose, dim3((d * ell + 255) / 256), dim3(256), 0, stream, R, d, ell, Rt);
     }
     const int vec4 = ((reinterpret_cast<uintptr_t>(X) & 15) == 0) && (ldx % 4 == 0) && (d % 4 == 0);
-    const int64_t ntiles = (n + LP_WAVES * 16 - 1) / (LP_WAVES * 16);
-    const int64_t grid = ntiles < (int64_t)ctx->num_cu * 4 ? ntiles : (int64_t)ctx->num_cu * 4;
-    {
+    const size_t lds_res = (size_t)nkc * NCB * 64 * sizeof(BT);
+    if (vec4 && nkc <= LP_KREG_CHUNKS) {
+        // R resident in LDS; one workgroup per CU, two when R is small
+        const void* f = reinterpret_cast<const void*>(&k_project_lp_res<DT, NCB>);
+        MSM_HIP(ctx, hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_res));
+        const int per_cu = lds_res <= 64 * 1024 ? 2 : 1;
+        const int64_t ntiles = (n + LPR_WAVES * 16 - 1) / (LPR_WAVES * 16);
+        const int64_t cap = (int64_t)ctx->num_cu * per_cu;
+        const int64_t grid = ntiles < cap ? ntiles : cap;
+        msm::KernelTimer kt(ctx, stream, DT == MSM_BF16 ? "k_project_bf16" : "k_project_fp8");
+        hipLaunchKernelGGL((k_project_lp_res<DT, NCB>), dim3((unsigned)grid), dim3(LPR_THREADS), lds_res, stream, X,
+                           n, d, ldx, (const float*)Rt, ell, (const BT*)Rp, (const float*)ib, S, W, nkc, tau,
+                           n_recomputed ? counter : nullptr);
+    } else {
+        const int64_t ntiles = (n + LP_WAVES * 16 - 1) / (LP_WAVES * 16);
+        const int64_t grid = ntiles < (int64_t)ctx->num_cu * 4 ? ntiles : (int64_t)ctx->num_cu * 4;
         msm::KernelTimer kt(ctx, stream, DT == MSM_BF16 ? "k_project_bf16" : "k_project_fp8");
         hipLaunchKernelGGL((k_project_lp<DT, NCB>), dim3((unsigned)grid), dim3(LP_THREADS), lds, stream, X, n, d,
                            ldx, (const float*)Rt, ell, (const BT*)Rp, (const float*)ib, S, W, kt_chunks, nkc, vec4, tau,
