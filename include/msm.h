@@ -313,12 +313,15 @@ typedef struct {
     int32_t reserved;
 } msm_instance;
 
-/* A tuning parameter set of the batched enumeration and its measured time. */
+/* A tuning parameter set of the batched enumeration for the instances with
+ * n_min <= n < n_max, and the measured time of the whole batch's
+ * enumeration with it. */
 typedef struct {
     int32_t bucket_target;     /* points per partition bucket aimed at */
     int32_t digit_bits;        /* width of the radix digit counted inside a bucket */
     int32_t buckets_per_group; /* buckets taken by one workgroup */
     float ms;                  /* enumeration time of the whole batch, -1 if untimed */
+    int64_t n_min, n_max;      /* the size class it applies to */
 } msm_batch_config;
 
 typedef struct msm_batch msm_batch;
@@ -326,10 +329,12 @@ typedef struct msm_batch msm_batch;
 /* Plan a batch: checks the instances, allocates the plan's device memory
  * (about 8 * N * min(C(k,h), groups) bytes of partition plus the
  * concatenated strings, N = total points) and uploads its tables. With
- * autotune != 0 every candidate configuration (bucket target 256, 512 or
- * 1024 points, digit 8, 10 or 12 bits, 2 or 8 buckets per workgroup) is
- * timed on this batch and the fastest kept; this runs the batch, so S and
- * pairs of the instances are written. The descriptors are copied: the
+ * autotune != 0 the candidate configurations (bucket target 256, 512 or
+ * 1024 points, digit 8, 10 or 12 bits, 2 or 8 buckets per workgroup) are
+ * timed on this batch for each class of instance size (n below 8192, below
+ * 65536, above) in turn, the other classes at their best so far, and each
+ * class keeps its fastest; this runs the batch, so S and pairs of the
+ * instances are written. The descriptors are copied: the
  * buffers they point to must stay valid for the plan's life.
  *   inst   HOST msm_instance[count], 1 <= count <= 65535
  *   out    HOST, receives the plan
@@ -355,10 +360,13 @@ msm_status msm_batch_run(msm_batch* b, int64_t* m_dev, void* stream);
  * finish (an event recorded after each launch), whichever stream it ran on. */
 msm_status msm_batch_launch_graph(msm_batch* b, int64_t* m_dev, void* stream);
 
-/* The configuration in use and, when the plan was tuned, every candidate
- * with its time (up to cap HOST records; *n_tried gets their number). */
-msm_status msm_batch_tuning(const msm_batch* b, msm_batch_config* chosen, msm_batch_config* tried,
-                            int32_t cap, int32_t* n_tried);
+/* The configuration in use for each size class that holds instances (up
+ * to chosen_cap HOST records, smallest class first; *n_chosen gets their
+ * number) and, when the plan was tuned, every candidate tried with its time
+ * (up to cap HOST records; *n_tried gets their number). Any of the
+ * outputs may be NULL with its cap 0. Errors: MSM_E_INVALID. */
+msm_status msm_batch_tuning(const msm_batch* b, msm_batch_config* chosen, int32_t chosen_cap, int32_t* n_chosen,
+                            msm_batch_config* tried, int32_t cap, int32_t* n_tried);
 
 /* Release a plan and its device memory; no run of it may be in flight.
  * NULL is ignored. */

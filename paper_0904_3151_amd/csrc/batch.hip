@@ -13,8 +13,12 @@
 // work counter.
 //
 // The bucket size aimed at, the width of the in-bucket radix digit and the
-// number of buckets per workgroup are chosen at plan creation by timing
-// every candidate on the batch itself.
+// number of buckets per workgroup are chosen per class of instance size
+// (all instances share ell, k and h, so the key width is the same for all):
+// the instances are laid out class by class (points, tiles and buckets),
+// the bucket kernel runs once per class with that class's digit and group,
+// and at plan creation each class's candidates are timed on the batch itself
+// while the other classes keep their best configuration so far.
 #include "msm_enum.h"
 
 #include <algorithm>
@@ -40,6 +44,18 @@ int bits_for(int64_t n, int target)
     return r;
 }
 
+// Size classes of instances: [0, 8192), [8192, 65536), [65536, 2^32).
+constexpr int NCLS = 3;
+constexpr int64_t CLS_LO[NCLS] = {0, 8192, 65536};
+constexpr int64_t CLS_HI[NCLS] = {8192, 65536, (int64_t)1 << 32};
+
+int class_of(int64_t n)
+{
+    int c = 0;
+    while (c + 1 < NCLS && n >= CLS_LO[c + 1]) ++c;
+    return c;
+}
+
 }  // namespace
 
 struct msm_batch {
@@ -49,6 +65,10 @@ struct msm_batch {
     int max_d = 1;
     std::vector<msm_instance> inst;  // the caller's descriptors
     std::vector<int64_t> off;        // first point of each instance
+    std::vector<int> ord;            // instances in layout order (by size class)
+    std::vector<int> cls;            // size class of each instance
+    int cls_b0[NCLS] = {0, 0, 0};    // buckets of each class: [cls_b0, cls_b1)
+    int cls_b1[NCLS] = {0, 0, 0};
     std::vector<Combo> combos;
     std::vector<uint64_t> bm;
     uint64_t valid[MAXW] = {0, 0, 0, 0};
@@ -74,14 +94,14 @@ struct msm_batch {
     unsigned long long* d_work = nullptr;
     uint32_t* d_pwork = nullptr;  // entry counter of the projection
 
-    // current configuration
-    Config cfg{512, 10, 8};
+    // current configuration, per size class
+    Config cfg[NCLS] = {{512, 10, 8}, {512, 10, 8}, {512, 10, 8}};
     int nt = 0;        // partition tiles
     int NB = 0;        // buckets
     int max_nbi = 1;   // largest bucket count of one instance
     uint64_t cnt_stride = 0;
     std::vector<msm_batch_config> tried;
-    msm_batch_config chosen{};
+    msm_batch_config chosen[NCLS] = {};
 
     // graph of one run, captured on a private stream
     hipStream_t cap_stream = nullptr;
@@ -129,8 +149,9 @@ Sizes sizes_for(const msm_batch& b, int target)
     return z;
 }
 
-// Builds and uploads the instance, tile and bucket tables of a configuration.
-msm_status set_config(msm_batch& b, const Config& c)
+// Builds and uploads the instance, tile and bucket tables of a
+// configuration (one per size class). Instances are laid out in b.ord.
+msm_status set_config(msm_batch& b, const Config (&c)[NCLS])
 {
     msm_ctx* ctx = b.ctx;
     std::vector<BInst> bi(b.count);
@@ -138,9 +159,16 @@ msm_status set_config(msm_batch& b, const Config& c)
     uint32_t tstart = 0, bstart = 0;
     uint64_t cnt_off = 0;
     int max_nbi = 1;
-    for (int i = 0; i < b.count; ++i) {
+    for (int q = 0; q < NCLS; ++q) b.cls_b0[q] = b.cls_b1[q] = 0;
+    int prev_cls = -1;
+    for (int i : b.ord) {
         const int64_t n = b.inst[i].n;
-        const int r = bits_for(n, c.target);
+        const int q = b.cls[i];
+        if (q != prev_cls) {
+            b.cls_b0[q] = (int)bstart;
+            prev_cls = q;
+        }
+        const int r = bits_for(n, c[q].target);
         const uint32_t ntl = (uint32_t)((n + BATCH_T - 1) / BATCH_T);
         BInst& e = bi[i];
         e.off = (uint64_t)b.off[i];
@@ -157,6 +185,7 @@ msm_status set_config(msm_batch& b, const Config& c)
         for (int x = 0; x < (1 << r); ++x) bucket_inst.push_back((uint32_t)i);
         tstart += ntl;
         bstart += 1u << r;
+        b.cls_b1[q] = (int)bstart;
         cnt_off += (uint64_t)ntl << r;
         max_nbi = std::max(max_nbi, 1 << r);
     }
@@ -164,7 +193,7 @@ msm_status set_config(msm_batch& b, const Config& c)
     if (!tile_inst.empty())
         MSM_HIP(ctx, hipMemcpy(b.d_tile_inst, tile_inst.data(), 4 * tile_inst.size(), hipMemcpyHostToDevice));
     MSM_HIP(ctx, hipMemcpy(b.d_bucket_inst, bucket_inst.data(), 4 * bucket_inst.size(), hipMemcpyHostToDevice));
-    b.cfg = c;
+    for (int q = 0; q < NCLS; ++q) b.cfg[q] = c[q];
     b.nt = (int)tstart;
     b.NB = (int)bstart;
     b.max_nbi = max_nbi;
@@ -172,19 +201,21 @@ msm_status set_config(msm_batch& b, const Config& c)
     return MSM_OK;
 }
 
+// The bucket kernel over buckets [ba.bk_lo, ba.bk_hi).
 template <int W, int DIGIT>
-void launch_bucket(const Params& p, const BatchArgs& ba, int NB, int cc, hipStream_t s)
+void launch_bucket(const Params& p, const BatchArgs& ba, int cc, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_bucket<W, DIGIT, true, BK_THREADS, false, BK_MAXB, 0, false>), dim3((NB + ba.group - 1) / ba.group, cc),
-                       dim3(BK_THREADS), 0, s, p, ba);
+    const int nb = ba.bk_hi - ba.bk_lo;
+    hipLaunchKernelGGL((k_bucket<W, DIGIT, true, BK_THREADS, false, BK_MAXB, 0, false>),
+                       dim3((nb + ba.group - 1) / ba.group, cc), dim3(BK_THREADS), 0, s, p, ba);
 }
 
 template <int W>
-void launch_bucket_digit(const Params& p, const BatchArgs& ba, int digit, int NB, int cc, hipStream_t s)
+void launch_bucket_digit(const Params& p, const BatchArgs& ba, int digit, int cc, hipStream_t s)
 {
-    if (digit <= 8) launch_bucket<W, 8>(p, ba, NB, cc, s);
-    else if (digit <= 10) launch_bucket<W, 10>(p, ba, NB, cc, s);
-    else launch_bucket<W, 12>(p, ba, NB, cc, s);
+    if (digit <= 8) launch_bucket<W, 8>(p, ba, cc, s);
+    else if (digit <= 10) launch_bucket<W, 10>(p, ba, cc, s);
+    else launch_bucket<W, 12>(p, ba, cc, s);
 }
 
 // Enqueues the enumeration of every instance; the strings are in d_S.
@@ -219,8 +250,8 @@ msm_status enqueue_enumerate(msm_batch& b, int64_t* m_dev, hipStream_t s, bool t
     p.list_count = b.d_ovfc;
     p.ovf2 = b.d_ovf2;
     p.ovf2_count = b.d_ovfc + 1;
-    BatchArgs ba{b.d_inst, b.d_tile_inst, b.d_bucket_inst, b.cnt_stride, b.cfg.group,
-                 reinterpret_cast<unsigned long long*>(m_dev)};
+    BatchArgs ba{b.d_inst, b.d_tile_inst, b.d_bucket_inst, b.cnt_stride, b.cfg[0].group,
+                 reinterpret_cast<unsigned long long*>(m_dev), 0, b.NB};
     const int big_grid = 2 * ctx->num_cu;
     for (int c0 = 0; c0 < b.C; c0 += b.Cg) {
         const int cc = std::min(b.Cg, b.C - c0);
@@ -244,7 +275,14 @@ msm_status enqueue_enumerate(msm_batch& b, int64_t* m_dev, hipStream_t s, bool t
                                (size_t)BATCH_T * 8 + (size_t)b.max_nbi * 8, s, p, ba, b.max_nbi);
             kt.reset();
             if (prof) kt.reset(new msm::KernelTimer(ctx, s, "k_bucket_batch"));
-            launch_bucket_digit<W>(p, ba, b.cfg.digit, b.NB, cc, s);
+            for (int q = 0; q < NCLS; ++q) {
+                if (b.cls_b1[q] <= b.cls_b0[q]) continue;
+                BatchArgs bq = ba;
+                bq.bk_lo = b.cls_b0[q];
+                bq.bk_hi = b.cls_b1[q];
+                bq.group = b.cfg[q].group;
+                launch_bucket_digit<W>(p, bq, b.cfg[q].digit, cc, s);
+            }
             kt.reset();
             // buckets above the first pass's capacity: a persistent second
             // pass with more threads and LDS, then tile pairs for the rest
@@ -285,8 +323,17 @@ msm_status enqueue(msm_batch& b, int64_t* m_dev, hipStream_t s, bool timed)
     }
 }
 
-// Times the enumeration under every candidate configuration (the strings
-// must be in d_S) and keeps the fastest.
+msm_status enqueue_enum_any(msm_batch& b, int64_t* m_dev, hipStream_t s)
+{
+    return b.W == 1 ? enqueue_enumerate<1>(b, m_dev, s, false)
+                    : (b.W == 2 ? enqueue_enumerate<2>(b, m_dev, s, false)
+                                : (b.W == 3 ? enqueue_enumerate<3>(b, m_dev, s, false)
+                                            : enqueue_enumerate<4>(b, m_dev, s, false)));
+}
+
+// Times the enumeration under the candidate configurations of each size
+// class in turn (the strings must be in d_S), the other classes at their
+// best so far, and keeps each class's fastest.
 msm_status autotune(msm_batch& b, int64_t* m_dev, hipStream_t s)
 {
     static const int targets[] = {256, 512, 1024};
@@ -296,47 +343,52 @@ msm_status autotune(msm_batch& b, int64_t* m_dev, hipStream_t s)
     hipEvent_t e0, e1;
     MSM_HIP(ctx, hipEventCreate(&e0));
     MSM_HIP(ctx, hipEventCreate(&e1));
-    float best = -1.f;
-    Config best_c = b.cfg;
+    Config best[NCLS];
+    for (int q = 0; q < NCLS; ++q) best[q] = b.cfg[q];
+    float best_ms[NCLS] = {-1.f, -1.f, -1.f};
+    bool present[NCLS] = {false, false, false};
+    for (int i = 0; i < b.count; ++i)
+        if (b.inst[i].n > 0) present[b.cls[i]] = true;
     msm_status st = MSM_OK;
-    for (int t : targets)
-        for (int dg : digits)
-            for (int g : groups) {
-                const Config c{t, dg, g};
-                MSM_HIP(ctx, hipStreamSynchronize(s));  // tables are replaced below
-                st = set_config(b, c);
-                if (st != MSM_OK) break;
-                hipLaunchKernelGGL(k_zero_u64, dim3((b.count + 255) / 256), dim3(256), 0, s,
-                                   reinterpret_cast<unsigned long long*>(m_dev), b.count);
-                st = b.W == 1 ? enqueue_enumerate<1>(b, m_dev, s, false)
-                              : (b.W == 2 ? enqueue_enumerate<2>(b, m_dev, s, false)
-                                          : (b.W == 3 ? enqueue_enumerate<3>(b, m_dev, s, false)
-                                                      : enqueue_enumerate<4>(b, m_dev, s, false)));
-                if (st != MSM_OK) break;
-                (void)hipEventRecord(e0, s);
-                st = b.W == 1 ? enqueue_enumerate<1>(b, m_dev, s, false)
-                              : (b.W == 2 ? enqueue_enumerate<2>(b, m_dev, s, false)
-                                          : (b.W == 3 ? enqueue_enumerate<3>(b, m_dev, s, false)
-                                                      : enqueue_enumerate<4>(b, m_dev, s, false)));
-                if (st != MSM_OK) break;
-                (void)hipEventRecord(e1, s);
-                if (hipEventSynchronize(e1) != hipSuccess) {
-                    st = msm::fail(ctx, MSM_E_HIP, "msm_batch_create: timing a configuration failed");
-                    break;
+    for (int q = 0; q < NCLS && st == MSM_OK; ++q) {
+        if (!present[q]) continue;
+        for (int t : targets)
+            for (int dg : digits)
+                for (int g : groups) {
+                    if (st != MSM_OK) break;
+                    Config c[NCLS];
+                    for (int x = 0; x < NCLS; ++x) c[x] = best[x];
+                    c[q] = Config{t, dg, g};
+                    MSM_HIP(ctx, hipStreamSynchronize(s));  // tables are replaced below
+                    st = set_config(b, c);
+                    if (st != MSM_OK) break;
+                    hipLaunchKernelGGL(k_zero_u64, dim3((b.count + 255) / 256), dim3(256), 0, s,
+                                       reinterpret_cast<unsigned long long*>(m_dev), b.count);
+                    st = enqueue_enum_any(b, m_dev, s);  // warm-up
+                    if (st != MSM_OK) break;
+                    (void)hipEventRecord(e0, s);
+                    st = enqueue_enum_any(b, m_dev, s);
+                    if (st != MSM_OK) break;
+                    (void)hipEventRecord(e1, s);
+                    if (hipEventSynchronize(e1) != hipSuccess) {
+                        st = msm::fail(ctx, MSM_E_HIP, "msm_batch_create: timing a configuration failed");
+                        break;
+                    }
+                    float ms = 0.f;
+                    (void)hipEventElapsedTime(&ms, e0, e1);
+                    b.tried.push_back(msm_batch_config{t, dg, g, ms, CLS_LO[q], CLS_HI[q]});
+                    if (best_ms[q] < 0.f || ms < best_ms[q]) {
+                        best_ms[q] = ms;
+                        best[q] = c[q];
+                    }
                 }
-                float ms = 0.f;
-                (void)hipEventElapsedTime(&ms, e0, e1);
-                b.tried.push_back(msm_batch_config{t, dg, g, ms});
-                if (best < 0.f || ms < best) {
-                    best = ms;
-                    best_c = c;
-                }
-            }
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (st != MSM_OK) return st;
-    b.chosen = msm_batch_config{best_c.target, best_c.digit, best_c.group, best};
-    return set_config(b, best_c);
+    for (int q = 0; q < NCLS; ++q)
+        b.chosen[q] = msm_batch_config{best[q].target, best[q].digit, best[q].group, best_ms[q], CLS_LO[q], CLS_HI[q]};
+    return set_config(b, best);
 }
 
 }  // namespace
@@ -387,9 +439,17 @@ extern "C" msm_status msm_batch_create(msm_ctx* ctx, const msm_instance* inst, i
     b->max_d = max_d;
     b->inst.assign(inst, inst + count);
     b->off.resize(count);
+    b->cls.resize(count);
+    b->ord.resize(count);
+    for (int i = 0; i < count; ++i) {
+        b->cls[i] = class_of(inst[i].n);
+        b->ord[i] = i;
+    }
+    // instances laid out class by class, in their order within a class
+    std::stable_sort(b->ord.begin(), b->ord.end(), [&](int x, int y) { return b->cls[x] < b->cls[y]; });
     {
         int64_t o = 0;
-        for (int i = 0; i < count; ++i) {
+        for (int i : b->ord) {
             b->off[i] = o;
             o += inst[i].n;
         }
@@ -493,9 +553,12 @@ extern "C" msm_status msm_batch_create(msm_ctx* ctx, const msm_instance* inst, i
         MSM_HIP(ctx, hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds));
     }
 
-    st = set_config(*b, Config{512, 10, 8});
-    if (st != MSM_OK) return st;
-    b->chosen = msm_batch_config{512, 10, 8, -1.f};
+    {
+        const Config c0[NCLS] = {{512, 10, 8}, {512, 10, 8}, {512, 10, 8}};
+        st = set_config(*b, c0);
+        if (st != MSM_OK) return st;
+        for (int q = 0; q < NCLS; ++q) b->chosen[q] = msm_batch_config{512, 10, 8, -1.f, CLS_LO[q], CLS_HI[q]};
+    }
     if (autotune_flag && N >= 2) {
         // project once, then time the enumeration under each candidate
         int64_t* m_tmp = nullptr;
@@ -567,12 +630,22 @@ extern "C" msm_status msm_batch_launch_graph(msm_batch* b, int64_t* m_dev, void*
     return MSM_OK;
 }
 
-extern "C" msm_status msm_batch_tuning(const msm_batch* b, msm_batch_config* chosen, msm_batch_config* tried,
-                                       int32_t cap, int32_t* n_tried)
+extern "C" msm_status msm_batch_tuning(const msm_batch* b, msm_batch_config* chosen, int32_t chosen_cap,
+                                       int32_t* n_chosen, msm_batch_config* tried, int32_t cap, int32_t* n_tried)
 {
     if (!b) return msm::fail(nullptr, MSM_E_INVALID, "msm_batch_tuning: batch is NULL");
-    if (cap < 0 || (cap > 0 && !tried)) return msm::fail(b->ctx, MSM_E_INVALID, "msm_batch_tuning: bad cap");
-    if (chosen) *chosen = b->chosen;
+    if (cap < 0 || (cap > 0 && !tried) || chosen_cap < 0 || (chosen_cap > 0 && !chosen))
+        return msm::fail(b->ctx, MSM_E_INVALID, "msm_batch_tuning: bad cap");
+    // the classes that hold instances, in order of size
+    int nc = 0;
+    for (int q = 0; q < NCLS; ++q) {
+        bool present = false;
+        for (int i = 0; i < b->count; ++i) present = present || (b->inst[i].n > 0 && b->cls[i] == q);
+        if (!present) continue;
+        if (nc < chosen_cap) chosen[nc] = b->chosen[q];
+        ++nc;
+    }
+    if (n_chosen) *n_chosen = nc;
     if (n_tried) *n_tried = (int32_t)b->tried.size();
     for (int i = 0; i < cap && i < (int)b->tried.size(); ++i) tried[i] = b->tried[i];
     return MSM_OK;

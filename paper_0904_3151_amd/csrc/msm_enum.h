@@ -160,6 +160,7 @@ struct BatchArgs {
     uint64_t cnt_stride;          // words of tile counts per combination
     int group;                    // buckets per workgroup
     unsigned long long* m_dev;    // per-instance pair counters
+    int bk_lo, bk_hi;             // buckets [bk_lo, bk_hi) of this launch of the bucket kernel
 };
 
 // The output finalizer of SplitMix64 (Steele, Lea and Flood, "Fast
@@ -839,8 +840,8 @@ __global__ __launch_bounds__(TH, (TH == BK_THREADS && W <= 2 && DIGIT <= 10) ? 4
     const uint32_t* base = LIST ? nullptr : p.base + (size_t)cl * (p.nb + 1);
     const uint64_t* part = LIST ? p.part : p.part + (size_t)cl * p.n;
     const int group = BATCH ? ba.group : BK_GROUP;
-    const int bk0 = LIST ? 0 : (int)blockIdx.x * group;
-    const int bk1 = LIST ? 0 : min(p.nb, bk0 + group);
+    const int bk0 = LIST ? 0 : (BATCH ? ba.bk_lo : 0) + (int)blockIdx.x * group;
+    const int bk1 = LIST ? 0 : min(BATCH ? ba.bk_hi : p.nb, bk0 + group);
     const uint32_t nlist = LIST ? min(*p.list_count, p.list_cap) : 0u;
     int dsh = 64 - p.r1 - DIGIT;
 

@@ -62,11 +62,13 @@ class Instance(ctypes.Structure):
 
 class BatchConfig(ctypes.Structure):
     _fields_ = [("bucket_target", ctypes.c_int32), ("digit_bits", ctypes.c_int32),
-                ("buckets_per_group", ctypes.c_int32), ("ms", ctypes.c_float)]
+                ("buckets_per_group", ctypes.c_int32), ("ms", ctypes.c_float),
+                ("n_min", ctypes.c_int64), ("n_max", ctypes.c_int64)]
 
     def as_dict(self):
-        return {"bucket_target": self.bucket_target, "digit_bits": self.digit_bits,
-                "buckets_per_group": self.buckets_per_group, "ms": round(float(self.ms), 4)}
+        return {"n_min": int(self.n_min), "n_max": int(self.n_max), "bucket_target": self.bucket_target,
+                "digit_bits": self.digit_bits, "buckets_per_group": self.buckets_per_group,
+                "ms": round(float(self.ms), 4)}
 
 
 class MSMError(RuntimeError):
@@ -127,8 +129,8 @@ def _load():
     lib.msm_batch_run.restype = i32
     lib.msm_batch_launch_graph.argtypes = [vp, vp, vp]
     lib.msm_batch_launch_graph.restype = i32
-    lib.msm_batch_tuning.argtypes = [vp, ctypes.POINTER(BatchConfig), ctypes.POINTER(BatchConfig), i32,
-                                     ctypes.POINTER(i32)]
+    lib.msm_batch_tuning.argtypes = [vp, ctypes.POINTER(BatchConfig), i32, ctypes.POINTER(i32),
+                                     ctypes.POINTER(BatchConfig), i32, ctypes.POINTER(i32)]
     lib.msm_batch_tuning.restype = i32
     lib.msm_batch_destroy.argtypes = [vp]
     lib.msm_batch_destroy.restype = None
@@ -533,12 +535,16 @@ class Batch:
         return self.pairs[i][: min(int(m), self.pairs[i].shape[0])]
 
     def tuning(self) -> dict:
-        chosen = BatchConfig()
+        """{"chosen": one configuration per size class present, "tried": every
+        candidate timed when the plan was tuned}."""
+        nc = ctypes.c_int32(0)
         nt = ctypes.c_int32(0)
-        _check(self.ctx, _lib.msm_batch_tuning(self._h, ctypes.byref(chosen), None, 0, ctypes.byref(nt)))
+        _check(self.ctx, _lib.msm_batch_tuning(self._h, None, 0, ctypes.byref(nc), None, 0, ctypes.byref(nt)))
+        chosen = (BatchConfig * max(1, nc.value))()
         tried = (BatchConfig * max(1, nt.value))()
-        _check(self.ctx, _lib.msm_batch_tuning(self._h, None, tried, nt.value, None))
-        return {"chosen": chosen.as_dict(), "tried": [tried[i].as_dict() for i in range(nt.value)]}
+        _check(self.ctx, _lib.msm_batch_tuning(self._h, chosen, nc.value, None, tried, nt.value, None))
+        return {"chosen": [chosen[i].as_dict() for i in range(nc.value)],
+                "tried": [tried[i].as_dict() for i in range(nt.value)]}
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

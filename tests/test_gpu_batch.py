@@ -46,6 +46,15 @@ def check_batch(b, inst, ell, h, m, strings=True):
         assert np.array_equal(got, want), f"instance {i}: pair set differs"
 
 
+def check_tuning(t, classes):
+    """One chosen configuration per size class present, each the fastest
+    of that class's 18 candidates."""
+    assert len(t["chosen"]) == classes and len(t["tried"]) == 18 * classes
+    for c in t["chosen"]:
+        mine = [x for x in t["tried"] if (x["n_min"], x["n_max"]) == (c["n_min"], c["n_max"])]
+        assert len(mine) == 18 and c["ms"] == min(x["ms"] for x in mine)
+
+
 def identical_rows(n, d, seed):
     rng = np.random.default_rng(seed)
     row = rng.standard_normal(d).astype(np.float32)
@@ -74,9 +83,7 @@ def test_batch_matches_definition(msm, ctx, ell, k, h, tune):
     torch.cuda.synchronize()
     check_batch(b, inst, ell, h, m)
     if tune:
-        t = b.tuning()
-        assert len(t["tried"]) == 18
-        assert t["chosen"]["ms"] == min(c["ms"] for c in t["tried"])
+        check_tuning(b.tuning(), classes=1)
     b.close()
 
 
@@ -180,6 +187,7 @@ def test_batch_workload_instances_match_oracle(msm, ctx):
     caps = [60 * X.shape[0] for X, _ in inst]
     announce("batch workload instances", [X.shape for X, _ in inst])
     b = msm.Batch(ctx, Xs, Rs, ell, k, h, caps, autotune=True)
+    check_tuning(b.tuning(), classes=3)   # n below 8192, below 65536 and above
     m = b.run().cpu().numpy()
     torch.cuda.synchronize()
     rng = np.random.default_rng(21)
