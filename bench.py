@@ -23,8 +23,8 @@ line for that form alone (batched: 512 independent instances in one
 captured graph; sweep: n from 125k to 2M and the all-identical worst case).
 
 Usage: python bench.py [--steps K] [--warmup W] [--cpu-sample N | --no-cpu-baseline]
-                       [--headline-only] [--workload paper|precision|learned|batched|sweep]
-                       [--epochs E] [--q-max Q]
+                       [--headline-only] [--reading radius|coord] [--pools Q | --q-max Q]
+                       [--workload paper|precision|learned|batched|sweep] [--epochs E]
 """
 import argparse
 import json
@@ -671,6 +671,10 @@ def run_batched(args):
            "hamming_pairs": int(m.sum()), "hamming_pairs_per_s": round(float(m.sum()) / (ms_graph / 1e3), 1),
            "instances_over_capacity": overflow,
            "ms_per_step_eager": round(ms_eager, 4), "ms_one_by_one": round(ms_seq, 2),
+           # time the kernels themselves take per step (events around each
+           # launch in the eager runs): the graph's time beyond it is launch
+           # gaps that one persistent kernel could remove
+           "kernel_sum_ms": round(sum(v["ms_per_step"] for v in phase.values()), 4),
            "one_by_one_counts_match": bool(same), "plan_and_tune_s": round(t_plan, 2), "autotune": tuning,
            "kernels": {q: {kk: round(vv, 4) if isinstance(vv, float) else vv for kk, vv in v.items()}
                        for q, v in sorted(phase.items())},
@@ -692,15 +696,22 @@ def run_paper(args):
 
     w = I.PAPER_SCALE
     target = 1e-3
-    log(f"generating {w.name} (radius)")
-    X, _ = I.workload_inputs(w, sigma_mode="radius")
+    reading = args.reading
+    log(f"generating {w.name} ({reading})")
+    X, _ = I.workload_inputs(w, sigma_mode=reading)
     n, W = w.n, (w.ell + 63) // 64
     dev = torch.device("cuda:0")
     Xd = torch.from_numpy(X).to(dev)
-    Rs_np = I.projection_matrices(w.d, w.ell, args.q_max, w.seed_r)
-    Rs = [torch.from_numpy(Rs_np[q]).to(dev) for q in range(args.q_max)]
+    q_top = max(args.q_max, args.pools)
+    Rs_np = I.projection_matrices(w.d, w.ell, q_top, w.seed_r)
+    Rs = [torch.from_numpy(Rs_np[q]).to(dev) for q in range(q_top)]
     ctx = msm.Context(0)
-    Q, q_table = choose_pools(msm, ctx, w, Xd, Rs, args.q_max, target)
+    if args.pools > 0 or reading == "coord":
+        # a fixed number of pools (the per-coordinate reading has no
+        # epsilon-pairs, so no ratio to choose it by)
+        Q, q_table = max(1, args.pools), None
+    else:
+        Q, q_table = choose_pools(msm, ctx, w, Xd, Rs, args.q_max, target)
 
     def project_pools(S, Q=Q):
         if Q == 1:
@@ -710,7 +721,7 @@ def run_paper(args):
                 msm.msm_project(ctx, Xd, Rs[q], S[q])
 
     res = run_mixture(msm, ctx, w, Xd, project_pools, args.steps, args.warmup, Q=Q)
-    tag = f"{w.name}:radius" + (f":q{Q}" if Q > 1 else "")
+    tag = f"{w.name}:{reading}" + (f":q{Q}" if Q > 1 else "")
     roof = roofline_of(res, w, n, W, tag)
     forms = {}
     errors = {}
@@ -730,7 +741,7 @@ def run_paper(args):
                              min(args.warmup, 2))
             return form_summary(r1, roofline_of(r1, w, n, W, f"{w.name}:radius"))
 
-        if Q > 1:
+        if Q > 1 and reading == "radius":
             attempt("single_pool_radius", single_pool)
 
         def coord():
@@ -743,7 +754,8 @@ def run_paper(args):
             out["note"] = "per-coordinate reading of sigma: no pair lies within eps, the ratio is undefined"
             return out
 
-        attempt("coord_reading", coord)
+        if reading == "radius":
+            attempt("coord_reading", coord)
     cpu = None
     if not args.no_cpu_baseline:
         sample = args.cpu_sample if 0 < args.cpu_sample < n else n
@@ -759,9 +771,9 @@ def run_paper(args):
     mr = res["missing_edge_ratio"]
     mr["target"] = target
     out = line(res["points_per_s"], res["ms_per_step"], args, "f32",
-               "synthetic Gaussian mixture, sigma_mode=radius",
+               f"synthetic Gaussian mixture, sigma_mode={reading}",
                {"workload": w.name, "n": n, "d": w.d, "ell": w.ell, "k": w.k, "h": w.h, "eps": w.eps,
-                "metric": w.metric, "sigma_mode": "radius", "pools": Q, "groupings": res["combinations"],
+                "metric": w.metric, "sigma_mode": reading, "pools": Q, "groupings": res["combinations"],
                 "hier_j": res["hier_j"],
                 "projection_arith": ("fp32 as three bf16 parts, six products, fp32 accumulation"
                                      if w.ell <= 128 and w.d <= 256 else "fp32 products")},
@@ -785,6 +797,10 @@ def main():
     ap.add_argument("--headline-only", action="store_true",
                     help="only the headline step (no other forms in the line)")
     ap.add_argument("--q-max", type=int, default=6, help="most string pools the headline may use")
+    ap.add_argument("--pools", type=int, default=0,
+                    help="string pools of the headline step (0: the least whose missing-edge ratio is <= 1e-3)")
+    ap.add_argument("--reading", default="radius", choices=["radius", "coord"],
+                    help="reading of the mixture's sigma for the headline step (cluster radius, or per coordinate)")
     ap.add_argument("--epochs", type=int, default=20, help="training epochs of the learned form")
     ap.add_argument("--train-h", type=int, default=0,
                     help="h of the training loss of the learned form (0: twice the workload's h)")

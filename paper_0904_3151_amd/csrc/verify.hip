@@ -2,14 +2,18 @@
 //
 // A team of VF_TEAM lanes handles one pair: each lane reads consecutive
 // 16-byte pieces of x_i and x_j (a team covers VF_TEAM * 16 contiguous bytes
-// per row per step), four steps at a time so that eight loads per lane are
-// in flight, accumulates in FP32, and the team reduces with DPP adds.
-// The next pair's indices are fetched while the current pair is computed.
-// The team leaders then append the kept pairs with one atomic per wave.
+// per row per step), two consecutive pairs and two steps at a time so that
+// eight loads per lane are in flight, accumulates in FP32, and the team
+// reduces with DPP adds. The next pairs' indices are fetched while the
+// current pairs are computed. The team leaders then append the kept pairs
+// with one LDS atomic per wave.
 //
-// The kernel is bound by the latency of the row gathers and by the
-// per-pair work every lane of a team repeats (indices, reduction, decision,
-// append): eight lanes per pair balance the two at d = 128.
+// The kernel is bound by the per-pair work every lane of a team repeats
+// (indices, addresses, reduction, decision, append: about 60 % VALU-busy
+// with eight lanes per pair at d = 128) and by the vector-memory path that
+// carries both rows of every pair. Four lanes per pair halve the repeated
+// work at the same bytes per pair; two lanes make each team's row pieces
+// too short for the memory path.
 #include "msm_internal.h"
 
 #include <type_traits>
@@ -19,21 +23,19 @@ namespace {
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 constexpr int VF_THREADS = 256;
-constexpr int VF_TEAM = 8;
+constexpr int VF_TEAM = 4;
 constexpr int VF_PP = 2;     // consecutive pairs a team takes per iteration
 constexpr int VF_OUT = 1024;  // staged kept pairs per workgroup
 constexpr int NUM_XCD = 8;
-static_assert(VF_TEAM == 8, "team_sum adds over eight lanes");
+static_assert(VF_TEAM == 4, "team_sum adds over the four lanes of a quad");
 
-// Sum over the eight lanes of a team with DPP adds: lanes xor 1 and xor 2
-// inside each quad, then each lane and its mirror in the half row (lane
-// 7 - l), which pairs the two quads. Every lane ends with the same sum (each
-// step adds the same two values in either order).
+// Sum over the four lanes of a team (a DPP quad) with DPP adds: lanes xor 1,
+// then lanes xor 2. Every lane ends with the same sum (each step adds the
+// same two values in either order).
 __device__ __forceinline__ float team_sum(float v)
 {
     v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));  // quad [1,0,3,2]
     v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, false));  // quad [2,3,0,1]
-    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x141, 0xF, 0xF, false)); // half mirror
     return v;
 }
 

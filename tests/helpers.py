@@ -26,20 +26,20 @@ def codes(pairs):
 
 def euclid_band(d, eps):
     """Half-width of the band around eps^2 inside which FP32 and FP64 may
-    disagree. The kernel gives each pair to a team of eight lanes: a lane
-    adds its d/8 squared differences in order with fused multiply-adds and
-    three levels of DPP adds sum the eight lane totals, so the computed sum
-    carries at most d/8 + 3 roundings of non-negative terms, plus 2u from
-    each rounded difference before squaring: |error| <= (d/8 + 5) u Delta^2
+    disagree. The kernel gives each pair to a team of four lanes: a lane
+    adds its d/4 squared differences in order with fused multiply-adds and
+    two levels of DPP adds sum the four lane totals, so the computed sum
+    carries at most d/4 + 2 roundings of non-negative terms, plus 2u from
+    each rounded difference before squaring: |error| <= (d/4 + 4) u Delta^2
     to first order. The band (d + 16) u eps^2 contains that bound with
-    margin (and also covers a team of sixteen lanes or a serial sum)."""
+    margin (and also covers teams of other sizes or a serial sum)."""
     return (d + 16) * U32 * eps * eps
 
 
 def cosine_band(d):
     """Band around eps for the cosine distance 1 - x.y / (|x| |y|): the dot
-    product and both squared norms carry at most d/8 + 3 roundings each
+    product and both squared norms carry at most d/4 + 2 roundings each
     (relative to sum |x_t y_t| <= |x| |y|), the square roots, product,
-    quotient and difference one each: |error| <= (d/4 + 10) u to first
+    quotient and difference one each: |error| <= (d/2 + 8) u to first
     order, inside the band (2d + 32) u."""
     return (2 * d + 32) * U32
