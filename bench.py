@@ -48,6 +48,15 @@ def log(*a):
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
 
+# What the hardware counters show bounds each dominant kernel besides its
+# algorithmic roofline (rocprofv3 SQ, TA and TD counters of the same
+# workloads, summarised in profiles/).
+LIMITERS = {
+    "k_verify": "vector-memory path carrying both rows of every candidate (radius: TA 0.91, TD 0.93 busy, VALU 0.40)",
+    "k_bucket": "latency of dependent LDS and string-gather steps (VALU 0.39-0.50, TA 0.33, TD 0.64 busy)",
+    "k_project_x3": "BF16 matrix cores 0.45 busy (six products per FP32 product)",
+}
+
 
 def measured_traffic(kernel, workload):
     """HBM bytes per launch of `kernel` on `workload` from the stored
@@ -311,10 +320,13 @@ def roofline_of(res, w, n, W, tag, hid=None):
     achieved = amount / (phase[dom]["avg_ms"] / 1e3)
     peak = {"mfma": FP32_MFMA_PEAK_TFLOPS, "mfma_bf16": BF16_MFMA_PEAK_TFLOPS}.get(bound, HBM_PEAK_GBS)
     traffic = measured_traffic(dom, tag) if bound == "hbm" else None
-    return {"kernel": dom, "bound": "mfma" if bound.startswith("mfma") else bound, "achieved": round(achieved, 2),
-            "peak": peak, "unit": unit, "frac": round(achieved / peak, 4),
-            "traffic": round(traffic / 1e9, 4) if traffic is not None else None,
-            "traffic_unit": "GB per launch", "algorithmic_per_launch": round(amount, 4)}
+    out = {"kernel": dom, "bound": "mfma" if bound.startswith("mfma") else bound, "achieved": round(achieved, 2),
+           "peak": peak, "unit": unit, "frac": round(achieved / peak, 4),
+           "traffic": round(traffic / 1e9, 4) if traffic is not None else None,
+           "traffic_unit": "GB per launch", "algorithmic_per_launch": round(amount, 4)}
+    if dom in LIMITERS:
+        out["limiter"] = LIMITERS[dom]
+    return out
 
 
 def compact(res, full_kernels=True):
