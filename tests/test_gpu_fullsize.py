@@ -85,3 +85,32 @@ def test_fullsize_verify_sampled_pairs(run):
     band = keyed[np.abs(dist ** 2 - eps64 ** 2) <= euclid_band(W.d, eps64)]
     assert np.isin(diff, band).all()
     assert run["kept"] <= m
+
+
+def test_fullsize_two_pools_sampled_rows(msm, ctx):
+    """The headline configuration: two string pools of the 1M-point
+    radius workload, their union with cross-pool dedup (eq. (5)). Every
+    pair appears once, and the partners of 64 sampled rows are exactly the
+    union over pools of their exhaustive Hamming partners."""
+    announce("fullsize two pools", W.name)
+    X, _ = I.workload_inputs(W, sigma_mode="radius")
+    Xd = torch.from_numpy(X).cuda()
+    del X
+    Rs = I.projection_matrices(W.d, W.ell, 2, W.seed_r)
+    S = torch.empty((2, W.n, 2), dtype=torch.int64, device="cuda")
+    for q in range(2):
+        msm.msm_project(ctx, Xd, torch.from_numpy(Rs[q]).cuda(), S[q])
+    P, m = msm.enumerate_pairs(ctx, S, W.ell, W.k, W.h, cap_hint=1 << 27)
+    torch.cuda.synchronize()
+    i = P[:, 0].to(torch.int64)
+    j = P[:, 1].to(torch.int64)
+    assert bool((i < j).all()) and bool((j < W.n).all())
+    c, _ = torch.sort(i * W.n + j)
+    assert not bool((c[1:] == c[:-1]).any()), "duplicate pairs"
+    rows = I.subsample_indices(W.n, 64, seed=W.seed_sub + 13)
+    pools = to_np_strings(S.reshape(2 * W.n, 2)).reshape(2, W.n, 2)
+    want = np.unique(np.concatenate([codes(O.hamming_partners(pools[q], W.h, rows)) for q in range(2)]))
+    rt = torch.from_numpy(rows).cuda()
+    sel = torch.isin(i, rt) | torch.isin(j, rt)
+    got = codes(to_np_pairs(P[sel].contiguous()))
+    assert want.size > 0 and np.array_equal(got, want), (got.size, want.size)
