@@ -165,6 +165,16 @@ def test_grouping_plan_follows_the_data(msm, ctx):
     assert (g, j) in ((15, 2), (70, 0))
 
 
+def test_enumerate_mostly_lone_strings(msm, ctx):
+    """The precision workload's layout (ell = 240, k = 10, h = 8, 45
+    groupings) on 40 000 strings of which 39 000 are uniform and 1 000 are
+    near copies: nearly every point is alone in its bucket and in its run,
+    and the few runs of two or more sit among many lone points. The set is
+    still the exhaustive one."""
+    S = I.random_strings(40_000, 240, seed=83, n_seeds=39_000, flips=6)
+    assert check(msm, ctx, S, 240, 10, 8) > 0
+
+
 @pytest.mark.parametrize("ell,k,h,groupings", [
     (128, 8, 4, 15),    # 16-character blocks, family bitmap in LDS
     (96, 12, 3, 20),    # 8-character blocks, 2^12 difference sets
