@@ -53,6 +53,8 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
 # workloads, summarised in profiles/).
 LIMITERS = {
     "k_verify": "vector-memory path carrying both rows of every candidate (radius: TA 0.91, TD 0.93 busy, VALU 0.40)",
+    "k_verify_h": "vector-memory path carrying both FP16 rows of every candidate (radius: TA 0.86, TD 0.92 busy, "
+                  "VALU 0.60)",
     "k_bucket": "latency of dependent LDS and string-gather steps (VALU 0.39-0.50, TA 0.33, TD 0.64 busy)",
     "k_project_x3": "BF16 matrix cores 0.45 busy (six products per FP32 product)",
 }
@@ -105,7 +107,8 @@ def algorithmic(kernel, w, n, C, mH, mE, W, launches=1, hid=None):
     points under each of the C groupings (C(k, h) combinations of masked
     blocks, or the hierarchical groupings that replace them) of one string
     pool, and writes its share (1 / `launches`) of the mH pairs; k_verify
-    covers the mH candidate pairs and the n rows; k_project_f32 the
+    covers the mH candidate pairs and the n rows (k_verify_h the same on
+    the rows' FP16 copy, k_half_rows the rounding of X); k_project_f32 the
     n x d x ell products (k_project_x3 makes each of them as six BF16
     products); the low-precision projections read X once; k_mlp_fused makes
     the network's 2 n (d hid + hid ell) products.
@@ -131,6 +134,12 @@ def algorithmic(kernel, w, n, C, mH, mE, W, launches=1, hid=None):
         # of X once (the two rows of every candidate are re-read through the
         # caches, not from HBM)
         return (mH * 8 + mE * 8 + n * 4 * w.d) / 1e9, "GB/s", "hbm"
+    if kernel == "k_verify_h":
+        # the same with the rows' FP16 copy and their 4-byte bounds
+        return (mH * 8 + mE * 8 + n * (2 * w.d + 4)) / 1e9, "GB/s", "hbm"
+    if kernel == "k_half_rows":
+        # X read once, its FP16 copy and the row bounds written
+        return n * (4 * w.d + 2 * w.d + 4) / 1e9, "GB/s", "hbm"
     return None
 
 

@@ -205,6 +205,11 @@ msm_status msm_enumerate_replicates(msm_ctx* ctx, const uint64_t* S, int64_t n, 
 /* Verification step of Section 4.1: keep the pairs of a list whose true
  * distance is at most eps (Definition 1.1). FP32 arithmetic: Euclidean
  * compares sum (x_t - y_t)^2 with eps^2; cosine compares eq. (2) with eps.
+ * Euclidean lists of at least n pairs are first decided on FP16 copies of
+ * the rows with a proven error bound: a pair outside the bound's band is
+ * kept or dropped exactly as the real-valued distance decides, and only the
+ * pairs inside it are evaluated in FP32 as above. The copies take
+ * n * (2 * ceil8(d) + 4) bytes of the context's device scratch.
  *   X      DEVICE float[n rows, ldx stride]
  *   pairs  DEVICE uint32[2 * m]         candidate pairs (i, j), both < n
  *   out    DEVICE uint32[2 * cap]       kept pairs (may alias nothing else)

@@ -22,19 +22,19 @@ def test_profile_only_times_one_kernel(msm, ctx):
     Xd, Rd = torch.from_numpy(X).cuda(), torch.from_numpy(R).cuda()
     announce("profile only")
     msm.msm_profile_reset(ctx)
-    msm.msm_profile_only(ctx, "k_verify")
+    msm.msm_profile_only(ctx, "k_bucket")
     msm.msm_profile_enable(ctx, True)
     one_step(msm, ctx, Xd, Rd, w)
     msm.msm_profile_enable(ctx, False)
     got = msm.msm_profile_read(ctx)
-    assert set(got) == {"k_verify"} and got["k_verify"][0] == 1 and got["k_verify"][1] > 0
+    assert set(got) == {"k_bucket"} and got["k_bucket"][0] >= 1 and got["k_bucket"][1] > 0
     msm.msm_profile_reset(ctx)
     msm.msm_profile_only(ctx, None)
     msm.msm_profile_enable(ctx, True)
     one_step(msm, ctx, Xd, Rd, w)
     msm.msm_profile_enable(ctx, False)
     every = msm.msm_profile_read(ctx)
-    assert {"k_bucket", "k_verify"} <= set(every)
+    assert "k_bucket" in every and {"k_verify", "k_verify_h"} & set(every)
     assert {"k_project_f32", "k_project_x3"} & set(every)
     msm.msm_profile_reset(ctx)
     with pytest.raises(msm.MSMError) as e:

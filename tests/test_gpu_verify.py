@@ -183,3 +183,91 @@ def test_verify_cosine_precision_shape_with_zero_rows(msm, ctx):
     Pd = torch.from_numpy(np.ascontiguousarray(zp).view(np.int32)).cuda()
     _, kz = msm.msm_verify(ctx, torch.from_numpy(X).cuda(), Pd, O.COSINE, 0.99)
     assert kz == 0
+
+
+def _verify_np(msm, ctx, X, pairs, metric, eps, pad_rows=0):
+    n, d = X.shape
+    Xd = torch.zeros((n + pad_rows, d), dtype=torch.float32, device="cuda")
+    Xd[:n].copy_(torch.from_numpy(X))
+    Pd = torch.from_numpy(np.ascontiguousarray(pairs, dtype=np.uint32).view(np.int32)).cuda()
+    out, kept = msm.msm_verify(ctx, Xd, Pd, metric, eps)
+    got = codes(to_np_pairs(out))
+    assert kept == len(got)
+    return got
+
+
+SAMPLE_MIN = 1 << 16   # pairs the FP32 kernel verifies before the form of the rest is chosen
+
+
+def _screen_chosen(X, pairs, eps):
+    """The library's rule, evaluated with the oracle: the FP16 screen takes
+    the pairs after the first max(2^16, m / 64) when the list has at least
+    n pairs and at least an eighth of that sample is kept."""
+    m = len(pairs)
+    m0 = min(m, max(SAMPLE_MIN, m // 64))
+    kept0 = len(O.verify(X, pairs[:m0], O.EUCLIDEAN, float(np.float32(eps))))
+    return m >= X.shape[0] and m0 < m and kept0 * 8 >= m0
+
+
+@pytest.mark.parametrize("d,eps,sigma", [(128, 0.5, (0.05, 0.3)), (100, 0.35, 0.25), (7, 0.12, 0.1),
+                                         (256, 0.6, (0.3, 0.5))])
+def test_verify_fp16_screen_matches_fp32_path(msm, ctx, d, eps, sigma):
+    """Euclidean lists of at least n pairs, mostly near ones, are screened
+    on FP16 rows with a proven bound and only the pairs inside it are
+    summed in FP32; the same list checked against an X padded with unused
+    rows (fewer pairs than rows) takes the FP32 kernel for every pair. The
+    two kept sets agree except inside the FP32 band, and match the FP64
+    oracle there. The list holds every pair of cluster mates (10 clusters of
+    200 rows), then random pairs."""
+    n = 2000
+    X, lab = I.gaussian_mixture(n, d, 10, sigma, seed=d + 5, sigma_mode="radius")
+    order = np.argsort(lab, kind="stable")
+    blocks = []
+    for c in range(10):
+        rows = np.sort(order[lab[order] == c])
+        i, j = np.triu_indices(rows.size, 1)
+        blocks.append(np.stack([rows[i], rows[j]], 1))
+    rng = np.random.default_rng(d)
+    a = rng.integers(0, n, 40_000)
+    b = rng.integers(0, n, 40_000)
+    keep = a != b
+    blocks.append(np.stack([np.minimum(a, b)[keep], np.maximum(a, b)[keep]], 1))
+    pairs = np.concatenate(blocks).astype(np.uint32)
+    assert _screen_chosen(X, pairs, eps)
+    announce("fp16 screen vs fp32", d, eps, len(pairs))
+    screened = _verify_np(msm, ctx, X, pairs, O.EUCLIDEAN, eps)
+    plain = _verify_np(msm, ctx, X, pairs, O.EUCLIDEAN, eps, pad_rows=len(pairs))
+    eps64 = float(np.float32(eps))
+    want_p, dist = O.verify(X, pairs, O.EUCLIDEAN, eps64, want_dist=True)
+    p64 = pairs.astype(np.uint64)
+    keyed = (p64[:, 0] << np.uint64(32)) | p64[:, 1]
+    band = keyed[np.abs(dist ** 2 - eps64 ** 2) <= euclid_band(d, eps64)]
+    assert np.isin(np.setxor1d(screened, plain), band).all()
+    assert np.isin(np.setxor1d(screened, codes(np.unique(want_p, axis=0))), band).all()
+    assert 0 < len(screened) < len(pairs)
+
+
+def test_verify_fp16_screen_edges(msm, ctx):
+    """The screen on rows its FP16 copy cannot hold or barely holds, in
+    groups of 60 rows whose every pair is listed: a group offset by 40 000
+    (beyond the screen's range: all its pairs are summed in FP32), a group
+    scaled into FP16's subnormal range, a group of zero rows, a group of
+    rows at distance eps (1 +- 1e-3) from their group's first row, and
+    groups of rows scattered around eps from each other."""
+    rng = np.random.default_rng(91)
+    n, d, G, eps = 3000, 40, 60, 0.25
+    base = 3.0 * rng.standard_normal((n // G, d))
+    scale = rng.uniform(0.5, 1.5, (n, 1)) * eps / np.sqrt(2 * d)
+    X = (base[np.arange(n) // G] + scale * rng.standard_normal((n, d))).astype(np.float32)
+    X[0:G] += np.float32(40000.0)
+    X[G:2 * G] *= np.float32(1e-6)
+    X[2 * G:3 * G] = 0.0
+    for r in range(3 * G + 1, 4 * G):
+        u = rng.standard_normal(d)
+        u /= np.linalg.norm(u)
+        X[r] = X[3 * G] + (eps * (1 + 1e-3 * rng.uniform(-1, 1)) * u).astype(np.float32)
+    i, j = np.triu_indices(G, 1)
+    pairs = np.concatenate([np.stack([g * G + i, g * G + j], 1) for g in range(n // G)]).astype(np.uint32)
+    assert _screen_chosen(X, pairs, eps)
+    kept, band = check(msm, ctx, X, pairs, O.EUCLIDEAN, eps)
+    assert kept > 0
