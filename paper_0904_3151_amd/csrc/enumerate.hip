@@ -317,7 +317,7 @@ msm_status run_enumerate(msm_ctx* ctx, const uint64_t* S, int64_t n, int ell, in
         }
         {
             msm::KernelTimer kt(ctx, stream, "k_bucket");
-            launch_bucket<W>(hm, false, dim3((nb + BK_GROUP - 1) / BK_GROUP, cc), stream, p);
+            launch_bucket<W>(hm, false, dim3((nb + bk_group<W>() - 1) / bk_group<W>(), cc), stream, p);
         }
         // Buckets above the first pass's capacity: a second pass with more
         // threads and LDS takes those up to its own capacity, then tile pairs

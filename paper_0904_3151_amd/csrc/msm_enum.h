@@ -60,7 +60,17 @@ constexpr int BK_MAXB = 4;                        // 64-element batches per wave
 constexpr int BK_CAP = BK_WAVES * 64 * BK_MAXB;   // largest bucket sorted in LDS
 constexpr int BK_PAIR_MAX = 128;                  // consecutive pairs per lane and round, at most
 static_assert(BK_PAIR_MAX <= 128, "a lane keeps its results in four 32-bit words");
-constexpr int BK_GROUP = 2;                       // buckets per workgroup
+// Buckets per workgroup of the first pass, and whether sibling buckets that
+// fit in LDS together are taken as one unit. With four-word strings the
+// kernel keeps few workgroups per CU and each bucket's gathers and barriers
+// are exposed: eight buckets per workgroup, siblings merged, measured 5-11 %
+// faster at ell = 240 on lone and on clustered points; with narrower strings
+// two buckets per workgroup, unmerged, measured best.
+template <int W>
+constexpr int bk_group() { return W >= 4 ? 8 : 2; }
+template <int W>
+constexpr bool bk_merge() { return W >= 4; }
+static_assert(bk_group<1>() % 2 == 0 && bk_group<4>() % 2 == 0, "sibling buckets share a workgroup");
 constexpr int BK_OUT = 512;                       // staged output pairs per workgroup
 constexpr int BK_DIGIT = 10;                      // mix bits counted inside a bucket
 constexpr int BK_DIGIT_L = 12;                    // the same in the second pass over large buckets
@@ -741,7 +751,7 @@ __device__ __forceinline__ bool in_family(const uint32_t* tab, uint32_t D)
 }
 
 // -------------------------------------------------------------------------
-// 2. buckets, BK_GROUP consecutive ones per workgroup
+// 2. buckets, bk_group<W>() consecutive ones per workgroup
 //
 // Inside a bucket one more radix digit (BK_DIGIT bits of the mix, below the
 // bucket bits) is counted in an LDS histogram; the count returned by each
@@ -839,18 +849,31 @@ __global__ __launch_bounds__(TH, (TH == BK_THREADS && W <= 2 && DIGIT <= 10) ? 4
     msm::PairStager<BK_OUT> out{obuf, &ocnt, &ogb, o_pairs, o_cap, o_counter};
     const uint32_t* base = LIST ? nullptr : p.base + (size_t)cl * (p.nb + 1);
     const uint64_t* part = LIST ? p.part : p.part + (size_t)cl * p.n;
-    const int group = BATCH ? ba.group : BK_GROUP;
+    const int group = BATCH ? ba.group : bk_group<W>();
     const int bk0 = LIST ? 0 : (BATCH ? ba.bk_lo : 0) + (int)blockIdx.x * group;
     const int bk1 = LIST ? 0 : min(BATCH ? ba.bk_hi : p.nb, bk0 + group);
     const uint32_t nlist = LIST ? min(*p.list_count, p.list_cap) : 0u;
-    int dsh = 64 - p.r1 - DIGIT;
+    const int dsh0 = 64 - p.r1 - DIGIT;
+    int dsh = dsh0;
+    // The first pass takes its buckets in units: two sibling buckets (keys
+    // that differ only in the last partition bit) that fit in LDS together
+    // form one unit, whose in-bucket digit starts one bit higher, at the
+    // sibling bit, so that the two never share a run; the unit's fixed
+    // latency (gathers, barriers) is paid once (bk_merge). Other buckets are
+    // units of their own. group is even, so siblings share a workgroup.
+    auto merged_at = [&](int b) {
+        return bk_merge<W>() && !LIST && !BATCH && ((b - bk0) & 1) == 0 && b + 1 < bk1 &&
+               base[b + 2] - base[b] <= (uint32_t)CAP;
+    };
+    int ub = bk0;               // first bucket of the next unit
+    bool um = merged_at(bk0);   // whether that unit is a merged pair
 
-    // keys of the current bucket, loaded one bucket ahead
+    // keys of the current unit, loaded one unit ahead
     uint64_t key[MAXB];
     uint32_t nbeg = 0, ncnt = 0;
     if (!LIST) {
         nbeg = base[bk0];
-        ncnt = base[bk0 + 1] - nbeg;
+        ncnt = base[bk0 + (um ? 2 : 1)] - nbeg;
 #pragma unroll
         for (int b = 0; b < MAXB; ++b) {
             const int pos = threadIdx.x + b * TH;
@@ -889,16 +912,19 @@ __global__ __launch_bounds__(TH, (TH == BK_THREADS && W <= 2 && DIGIT <= 10) ? 4
                 cur[b] = (cnt <= (uint32_t)CAP && pos < (int)cnt) ? part[beg + pos] : ~0ull;
             }
         } else {
-            const int bk = bk0 + it;
-            if (bk >= bk1) break;
+            if (ub >= bk1) break;
             beg = nbeg;
             cnt = ncnt;
+            dsh = dsh0 + (um ? 1 : 0);
 #pragma unroll
             for (int b = 0; b < MAXB; ++b) cur[b] = key[b];
-            has_next = bk + 1 < bk1;
+            const int bk = ub;
+            ub += um ? 2 : 1;
+            has_next = ub < bk1;
             if (has_next) {
-                nbeg = base[bk + 1];
-                ncnt = base[bk + 2] - nbeg;
+                um = merged_at(ub);
+                nbeg = base[ub];
+                ncnt = base[ub + (um ? 2 : 1)] - nbeg;
 #pragma unroll
                 for (int b = 0; b < MAXB; ++b) {
                     const int pos = threadIdx.x + b * TH;
