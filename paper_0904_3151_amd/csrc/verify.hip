@@ -243,10 +243,11 @@ __global__ __launch_bounds__(VF_THREADS) void k_verify(const float* __restrict__
 // A team of four lanes (k_verify's layout on 16-byte pieces of eight halves)
 // forms t_k = fl16(h_ik - h_jk) with packed FP16 subtractions and
 // accumulates S = sum t_k^2 with FP32 fused multiply-adds on the halves.
-// Every t_k is within 2^-11 |h_ik - h_jk| + 2^-14 of the exact difference
-// of the FP16 rows, so with A = b_i + b_j, c = 2^-13 sqrt(d) and gamma a
-// bound on the relative error of the FP32 sum, the distance D of the FP32
-// rows satisfies
+// Every t_k, as the FMA reads it, is within 2^-11 |h_ik - h_jk| + 2 * 2^-14
+// of the exact difference of the FP16 rows (a subnormal result of the
+// subtraction, a flush inside the FMA), so with A = b_i + b_j,
+// c = 2^-13 sqrt(d) and gamma a bound on the relative error of the FP32
+// sum, the distance D of the FP32 rows satisfies
 //     (sqrt(S / (1 + gamma)) - c) / (1 + 2^-11) - A  <=  D
 //     D  <=  (sqrt(S / (1 - gamma)) + c) / (1 - 2^-11) + A.
 // The pair is kept for certain when S <= ((eps - A)(1 - 2^-11) - c)^2 (1 - gamma)
