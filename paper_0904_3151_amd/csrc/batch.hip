@@ -289,9 +289,9 @@ msm_status enqueue_enumerate(msm_batch& b, int64_t* m_dev, hipStream_t s, bool t
             const uint32_t ovf_cap = (uint32_t)cc * (uint32_t)b.NB;
             p.list_cap = ovf_cap;
             if (prof) kt.reset(new msm::KernelTimer(ctx, s, "k_bucket_large_batch"));
-            hipLaunchKernelGGL((k_bucket<W, BK_DIGIT_L, true, LARGE_THREADS, true, large_maxb<W>(), 0, false>),
+            hipLaunchKernelGGL((k_bucket<W, BK_DIGIT_L, true, large_threads<W>(), true, large_maxb<W>(), 0, false>),
                                dim3((unsigned)std::min<uint32_t>(ovf_cap, (uint32_t)big_grid)),
-                               dim3(LARGE_THREADS), 0, s, p, ba);
+                               dim3(large_threads<W>()), 0, s, p, ba);
             kt.reset();
             if (prof) kt.reset(new msm::KernelTimer(ctx, s, "k_big_batch"));
             hipLaunchKernelGGL(k_ovf_prefix, dim3(1), dim3(1024), 0, s, b.d_ovf2, b.d_ovfc + 1, ovf_cap, b.d_tile0);

@@ -17,8 +17,8 @@ template <int W, int HM, bool GT>
 void launch_bucket_mode(bool large, dim3 grid, hipStream_t stream, const Params& p)
 {
     if (large)
-        hipLaunchKernelGGL((k_bucket<W, BK_DIGIT_L, false, LARGE_THREADS, true, large_maxb<W>(), HM, GT>), grid,
-                           dim3(LARGE_THREADS), 0, stream, p, BatchArgs{});
+        hipLaunchKernelGGL((k_bucket<W, BK_DIGIT_L, false, large_threads<W>(), true, large_maxb<W>(), HM, GT>),
+                           grid, dim3(large_threads<W>()), 0, stream, p, BatchArgs{});
     else
         hipLaunchKernelGGL((k_bucket<W, BK_DIGIT, false, BK_THREADS, false, BK_MAXB, HM, GT>), grid,
                            dim3(BK_THREADS), 0, stream, p, BatchArgs{});

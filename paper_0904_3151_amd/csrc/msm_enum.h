@@ -85,11 +85,18 @@ constexpr int DT_LDS_WORDS = 1 << (DT_LDS_K - 5);
 
 // Threads and points per thread of the second bucket pass, sized so that
 // its LDS stays below 160 KB (capacity 4096 points for W <= 2, else 2048).
-constexpr int LARGE_THREADS = 512;
+// One workgroup fits a CU; with strings of one or two words it takes 1024
+// threads of four points each (512 threads of eight measured 0.71 against
+// 0.49 ms on the two-pool paper-scale step), with wider strings 512.
+template <int W>
+constexpr int large_threads()
+{
+    return W <= 2 ? 1024 : 512;
+}
 template <int W>
 constexpr int large_maxb()
 {
-    return W <= 2 ? 8 : 4;
+    return 4;
 }
 
 struct Combo {                    // one set B of masked blocks (or, grouped
@@ -1154,7 +1161,7 @@ __global__ __launch_bounds__(TH, (TH == BK_THREADS && W <= 2 && DIGIT <= 10) ? 4
         // round with every lane busy. It keeps the results in a bit mask and
         // appends the passing pairs once per round, walking its pairs a
         // second time for their point indices.
-        constexpr uint32_t PMAX = LIST ? BK_PAIR_MAX / 2 : BK_PAIR_MAX;  // the second pass has twice the lanes
+        constexpr uint32_t PMAX = LIST ? BK_PAIR_MAX / 2 : BK_PAIR_MAX;  // the second pass has more lanes
         const int cpl = (int)min(PMAX, (P + TH - 1) / TH);
         // next pair in row-major order over the live runs; the walk keeps
         // the member slots ia < ib of the pair and the end e of its run
