@@ -19,7 +19,10 @@ void launch_bucket_mode(bool large, dim3 grid, hipStream_t stream, const Params&
     if (large)
         hipLaunchKernelGGL((k_bucket<W, BK_DIGIT_L, false, large_threads<W>(), true, large_maxb<W>(), HM, GT>),
                            grid, dim3(large_threads<W>()), 0, stream, p, BatchArgs{});
-    else
+    else if (W >= 3 || p.rep > 0)
+        hipLaunchKernelGGL((k_bucket<W, BK_DIGIT, false, BK_THREADS_WIDE, false, BK_MAXB_WIDE, HM, GT>), grid,
+                           dim3(BK_THREADS_WIDE), 0, stream, p, BatchArgs{});
+    else if constexpr (W <= 2)
         hipLaunchKernelGGL((k_bucket<W, BK_DIGIT, false, BK_THREADS, false, BK_MAXB, HM, GT>), grid,
                            dim3(BK_THREADS), 0, stream, p, BatchArgs{});
 }

@@ -58,6 +58,16 @@ constexpr int BK_THREADS = 256;
 constexpr int BK_WAVES = BK_THREADS / 64;
 constexpr int BK_MAXB = 4;                        // 64-element batches per wave
 constexpr int BK_CAP = BK_WAVES * 64 * BK_MAXB;   // largest bucket sorted in LDS
+// The first pass with twice the threads at the same capacity, for strings of
+// three or four words and for later string pools (which test each passing
+// pair's strings in the earlier pools): more waves to hide the gathers.
+// Measured at paper scale: radius, second pool 1.63 -> 1.32 ms; ell = 240
+// radius 3.33 -> 2.44 ms, coord 3.26 -> 2.63 ms; ell = 192 radius 2.80 ->
+// 2.28 ms; but one-pool radius 1.09 -> 1.17 ms and coord 0.67 -> 0.83 ms at
+// ell = 128, which keep 256 threads.
+constexpr int BK_THREADS_WIDE = 512;
+constexpr int BK_MAXB_WIDE = 2;
+static_assert(BK_THREADS_WIDE * BK_MAXB_WIDE == BK_CAP, "both first-pass shapes hold the same buckets");
 constexpr int BK_PAIR_MAX = 128;                  // consecutive pairs per lane and round, at most
 static_assert(BK_PAIR_MAX <= 128, "a lane keeps its results in four 32-bit words");
 // Buckets per workgroup of the first pass, and whether sibling buckets that
@@ -780,7 +790,7 @@ __device__ __forceinline__ bool in_family(const uint32_t* tab, uint32_t D)
 // The first pass for W <= 2 fits four workgroups per CU in LDS; its
 // register budget is held to the matching four waves per SIMD.
 template <int W, int DIGIT, bool BATCH, int TH, bool LIST, int MAXB, int HM, bool GT>
-__global__ __launch_bounds__(TH, (TH == BK_THREADS && W <= 2 && DIGIT <= 10) ? 4 : 1) void k_bucket(Params p,
+__global__ __launch_bounds__(TH, (!LIST && W <= 2 && DIGIT <= 10) ? 4 : 1) void k_bucket(Params p,
                                                                                                    BatchArgs ba)
 {
     constexpr bool HIER = HM > 0;
