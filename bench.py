@@ -54,8 +54,8 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
 LIMITERS = {
     "k_verify": "vector-memory path carrying both rows of every candidate (radius: TA 0.91, TD 0.93 busy, VALU 0.40)",
     "k_verify_h": "vector-memory path carrying both FP16 rows of every candidate (radius: TA 0.86, TD 0.92 busy, "
-                  "VALU 0.60)",
-    "k_bucket": "latency of dependent LDS and string-gather steps (VALU 0.39-0.50, TA 0.33, TD 0.64 busy)",
+                  "VALU 0.58)",
+    "k_bucket": "latency of dependent LDS and string-gather steps (VALU 0.46-0.59, TA 0.24-0.40, TD 0.35-0.61 busy)",
     "k_project_x3": "BF16 matrix cores 0.45 busy (six products per FP32 product)",
 }
 

@@ -266,7 +266,7 @@ constexpr int VH_TEAM = 4;             // lanes per pair in the screen
 // the FP32 kernel verifies the first max(VH_SAMPLE_MIN, m / VH_SAMPLE_DIV)
 // pairs, from which the form of the rest is chosen
 constexpr int64_t VH_SAMPLE_MIN = 1 << 16;
-constexpr int64_t VH_SAMPLE_DIV = 64;
+constexpr int64_t VH_SAMPLE_DIV = 256;
 
 __device__ __forceinline__ half2v as_h2(uint32_t u) { return __builtin_bit_cast(half2v, u); }
 

@@ -201,10 +201,10 @@ SAMPLE_MIN = 1 << 16   # pairs the FP32 kernel verifies before the form of the r
 
 def _screen_chosen(X, pairs, eps):
     """The library's rule, evaluated with the oracle: the FP16 screen takes
-    the pairs after the first max(2^16, m / 64) when the list has at least
+    the pairs after the first max(2^16, m / 256) when the list has at least
     n pairs and at least an eighth of that sample is kept."""
     m = len(pairs)
-    m0 = min(m, max(SAMPLE_MIN, m // 64))
+    m0 = min(m, max(SAMPLE_MIN, m // 256))
     kept0 = len(O.verify(X, pairs[:m0], O.EUCLIDEAN, float(np.float32(eps))))
     return m >= X.shape[0] and m0 < m and kept0 * 8 >= m0
 
