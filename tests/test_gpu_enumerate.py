@@ -175,6 +175,16 @@ def test_enumerate_mostly_lone_strings(msm, ctx):
     assert check(msm, ctx, S, 240, 10, 8) > 0
 
 
+def test_enumerate_wide_strings_many_buckets(msm, ctx):
+    """Four-word strings (ell = 240, k = 10, h = 8) over 64 partition
+    buckets per grouping, in clusters of about ten strings within a few
+    flips of a seed: the first pass's wide shape takes eight buckets per
+    workgroup and merges sibling buckets that fit in LDS together, next to
+    buckets that do not fit. The set is the exhaustive one."""
+    S = I.random_strings(30_000, 240, seed=97, n_seeds=3000, flips=5)
+    assert check(msm, ctx, S, 240, 10, 8, cap_hint=1 << 18) > 0
+
+
 @pytest.mark.parametrize("ell,k,h,groupings", [
     (128, 8, 4, 15),    # 16-character blocks, family bitmap in LDS
     (96, 12, 3, 20),    # 8-character blocks, 2^12 difference sets
