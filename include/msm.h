@@ -209,7 +209,8 @@ msm_status msm_enumerate_replicates(msm_ctx* ctx, const uint64_t* S, int64_t n, 
  * the rows with a proven error bound: a pair outside the bound's band is
  * kept or dropped exactly as the real-valued distance decides, and only the
  * pairs inside it are evaluated in FP32 as above. The copies take
- * n * (2 * ceil8(d) + 4) bytes of the context's device scratch.
+ * n * (2 * ceil8(d) + 4) bytes of the context's device scratch; when that
+ * memory cannot be had, the FP32 kernel verifies the whole list.
  *   X      DEVICE float[n rows, ldx stride]
  *   pairs  DEVICE uint32[2 * m]         candidate pairs (i, j), both < n
  *   out    DEVICE uint32[2 * cap]       kept pairs (may alias nothing else)

@@ -590,11 +590,17 @@ extern "C" msm_status msm_verify(msm_ctx* ctx, const float* X, int64_t n, int32_
     // The FP16 screen pays for rounding the rows once when the list has at
     // least as many pairs as X has rows (and most of them are near: see
     // k_choose_form).
-    const bool screen = metric == MSM_EUCLIDEAN && m >= n;
+    bool screen = metric == MSM_EUCLIDEAN && m >= n;
     const int64_t ldw = ((int64_t)d + 7) / 8 * 4;  // 32-bit words of an FP16 row
     const size_t bnd_bytes = msm::align_up((size_t)n * sizeof(float), 256);
     void* scr = nullptr;
     st = msm::ctx_scratch(ctx, screen ? 256 + bnd_bytes + (size_t)n * (size_t)ldw * 4 : 256, s, &scr);
+    if (st == MSM_E_NOMEM && screen) {
+        // no room for the FP16 copy: the FP32 kernel verifies the whole list
+        ctx->err.clear();
+        screen = false;
+        st = msm::ctx_scratch(ctx, 256, s, &scr);
+    }
     if (st != MSM_OK) return st;
     unsigned long long* counter = static_cast<unsigned long long*>(scr);
     uint32_t* bad = reinterpret_cast<uint32_t*>(counter + 1);
