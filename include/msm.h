@@ -69,8 +69,12 @@ int32_t msm_version(void);
 
 /* Create a context on HIP device `device`. The context owns the scratch
  * memory of the calls made through it; it grows on demand and is released
- * by msm_destroy. Returns MSM_E_INVALID if out is NULL, MSM_E_HIP if the
- * device cannot be selected. */
+ * by msm_destroy. Calls through one context share that memory: make them
+ * from one host thread, on one stream, or wait for the previous call's work
+ * before a call on another stream (a call that grows the scratch waits only
+ * for its own stream before releasing the old buffer). Returns
+ * MSM_E_INVALID if out is NULL, MSM_E_HIP if the device cannot be
+ * selected. */
 msm_status msm_create(int32_t device, msm_ctx** out);
 
 /* Release a context and its scratch memory. NULL is ignored. The caller
