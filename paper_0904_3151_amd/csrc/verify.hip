@@ -41,18 +41,6 @@ __device__ __forceinline__ float team_sum(float v)
     return v;
 }
 
-// Sum over a team of four or eight lanes: the quad sum, then (eight lanes)
-// the other quad's sum through a half-row mirror. Every lane of the team
-// ends with the same value.
-template <int TEAM>
-__device__ __forceinline__ float team_sum_of(float v)
-{
-    v = team_sum(v);
-    if constexpr (TEAM == 8)
-        v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x141, 0xF, 0xF, false));
-    return v;
-}
-
 template <int METRIC, bool VEC4>
 __global__ __launch_bounds__(VF_THREADS) void k_verify(const float* __restrict__ X, int64_t n, int d,
                                                        int64_t ldx, const uint32_t* __restrict__ pairs,
@@ -262,7 +250,6 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 constexpr float VH_MAXABS = 32752.0f;  // largest FP16 value at most half the FP16 maximum
 constexpr int VH_ROW_LANES = 16;       // lanes per row in the rounding kernel
 constexpr int VH_ROWS = 256 / VH_ROW_LANES;
-constexpr int VH_TEAM = 4;             // lanes per pair in the screen
 // the FP32 kernel verifies the first max(VH_SAMPLE_MIN, m / VH_SAMPLE_DIV)
 // pairs, from which the form of the rest is chosen
 constexpr int64_t VH_SAMPLE_MIN = 1 << 16;
@@ -352,7 +339,7 @@ __global__ __launch_bounds__(256) void k_half_rows(const float* __restrict__ X, 
     }
 }
 
-template <bool VEC4, int TEAM>
+template <bool VEC4>
 __global__ __launch_bounds__(VF_THREADS) void k_verify_h(const uint32_t* __restrict__ Xh, int64_t ldw,
                                                          const float* __restrict__ bnd,
                                                          const float* __restrict__ X, int64_t n, int d,
@@ -369,12 +356,12 @@ __global__ __launch_bounds__(VF_THREADS) void k_verify_h(const uint32_t* __restr
     if (threadIdx.x == 0) ocnt = 0;
     __syncthreads();
     msm::PairStager<VF_OUT> stage{obuf, &ocnt, &ogb, out, cap, counter};
-    const int tl = threadIdx.x & (TEAM - 1);
+    const int tl = threadIdx.x & (VF_TEAM - 1);
     const int xcd = (int)(blockIdx.x % NUM_XCD);
     const int64_t per_die = gridDim.x / NUM_XCD;
     const int64_t lo = m * xcd / NUM_XCD, hi = m * (xcd + 1) / NUM_XCD;
-    const int64_t team = ((int64_t)(blockIdx.x / NUM_XCD) * VF_THREADS + threadIdx.x) / TEAM;
-    const int64_t nteams = (per_die * VF_THREADS) / TEAM;
+    const int64_t team = ((int64_t)(blockIdx.x / NUM_XCD) * VF_THREADS + threadIdx.x) / VF_TEAM;
+    const int64_t nteams = (per_die * VF_THREADS) / VF_TEAM;
     const int64_t span = nteams * VF_PP;
     const int64_t rounds = (hi - lo + span - 1) / span;
     const float eps2 = eps * eps;
@@ -431,7 +418,7 @@ __global__ __launch_bounds__(VF_THREADS) void k_verify_h(const uint32_t* __restr
             a[pp] = fmaf((float)t[0], (float)t[0], a[pp]);
             a[pp] = fmaf((float)t[1], (float)t[1], a[pp]);
         };
-        constexpr int STEPW = TEAM * 4;  // words of a team step
+        constexpr int STEPW = VF_TEAM * 4;  // words of a team step
         auto rows = [&](auto check_tag) {
             constexpr bool CHECK = decltype(check_tag)::value;
             // while checking, one team step (32 coordinates) between checks
@@ -462,7 +449,7 @@ __global__ __launch_bounds__(VF_THREADS) void k_verify_h(const uint32_t* __restr
                     bool all_far = true;
 #pragma unroll
                     for (int pp = 0; pp < VF_PP; ++pp) {
-                        if (!far[pp]) far[pp] = team_sum_of<TEAM>(a[pp]) > rej_thr(bi[pp], bj[pp]);
+                        if (!far[pp]) far[pp] = team_sum(a[pp]) > rej_thr(bi[pp], bj[pp]);
                         all_far = all_far && far[pp];
                     }
                     if (all_far) break;
@@ -486,7 +473,7 @@ __global__ __launch_bounds__(VF_THREADS) void k_verify_h(const uint32_t* __restr
         uint32_t nlive = 0, nrej = 0;
 #pragma unroll
         for (int pp = 0; pp < VF_PP; ++pp) {
-            const float sum = team_sum_of<TEAM>(a[pp]);
+            const float sum = team_sum(a[pp]);
             // every lane of a team holds the same sum and bounds, so the
             // branch below is taken by whole teams
             bool keep = false, undecided = false;
@@ -497,11 +484,10 @@ __global__ __launch_bounds__(VF_THREADS) void k_verify_h(const uint32_t* __restr
             if (undecided) {
                 const float* xi = X + (int64_t)pi[pp] * ldx;
                 const float* xj = X + (int64_t)pj[pp] * ldx;
-                // each quad of the team sums as k_verify's four lanes do
-                const int ql = tl & (VF_TEAM - 1);
+                // the team sums as k_verify's four lanes do
                 float s32 = 0.f;
                 if (VEC4) {
-                    for (int t = ql * 4; t < d; t += VF_TEAM * 4) {
+                    for (int t = tl * 4; t < d; t += VF_TEAM * 4) {
                         const floatx4 u = *reinterpret_cast<const floatx4*>(xi + t);
                         const floatx4 v = *reinterpret_cast<const floatx4*>(xj + t);
 #pragma unroll
@@ -511,7 +497,7 @@ __global__ __launch_bounds__(VF_THREADS) void k_verify_h(const uint32_t* __restr
                         }
                     }
                 } else {
-                    for (int t = ql; t < d; t += VF_TEAM) {
+                    for (int t = tl; t < d; t += VF_TEAM) {
                         const float e = xi[t] - xj[t];
                         s32 = fmaf(e, e, s32);
                     }
@@ -645,10 +631,10 @@ extern "C" msm_status msm_verify(msm_ctx* ctx, const float* X, int64_t n, int32_
         {
             msm::KernelTimer kt(ctx, s, "k_verify_h");
             if (vec4)
-                hipLaunchKernelGGL((k_verify_h<true, VH_TEAM>), grid, dim3(VF_THREADS), 0, s, Xh, ldw, bnd, X, n, d,
+                hipLaunchKernelGGL((k_verify_h<true>), grid, dim3(VF_THREADS), 0, s, Xh, ldw, bnd, X, n, d,
                                    ldx, rest, mr, eps, kc, out, (unsigned long long)cap, counter, bad, run);
             else
-                hipLaunchKernelGGL((k_verify_h<false, VH_TEAM>), grid, dim3(VF_THREADS), 0, s, Xh, ldw, bnd, X, n,
+                hipLaunchKernelGGL((k_verify_h<false>), grid, dim3(VF_THREADS), 0, s, Xh, ldw, bnd, X, n,
                                    d, ldx, rest, mr, eps, kc, out, (unsigned long long)cap, counter, bad, run);
         }
         msm::KernelTimer kt(ctx, s, "k_verify");
