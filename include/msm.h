@@ -354,8 +354,10 @@ typedef struct msm_batch msm_batch;
 msm_status msm_batch_create(msm_ctx* ctx, const msm_instance* inst, int32_t count, int32_t ell,
                             int32_t k, int32_t h, int32_t autotune, msm_batch** out, void* stream);
 
-/* Enqueue one run of the batch on `stream`: projection of every instance,
- * then its Hamming pairs. Only kernel launches are enqueued (counters are
+/* Enqueue one run of the batch on `stream`: projection of every instance
+ * (the arithmetic of msm_project: for ell <= 128 and d <= 256 the three-part
+ * BF16 split with six products, else FP32 products), then its Hamming
+ * pairs. Only kernel launches are enqueued (counters are
  * cleared by kernels, nothing is copied, nothing waits on the host), so the
  * call may be captured into a HIP graph.
  *   m_dev  DEVICE int64[count]: pairs of each instance. When m_dev[i] >

@@ -387,6 +387,143 @@ msm_status launch_x3(msm_ctx* ctx, const float* X, int64_t n, int d, int64_t ldx
     return MSM_OK;
 }
 
+// Batched projection in the split form (three BF16 parts, six products per
+// FP32 product, as k_project_x3) for ell <= 128 when the parts of R fit in
+// LDS: workgroups claim entries (runs of rows of one instance) from a
+// device counter as k_project_batch does, split the entry's instance's R
+// into LDS as deep as its d, and each wave takes 16 rows at a time.
+constexpr int BX3_THREADS = 256;
+constexpr int BX3_WAVES = BX3_THREADS / 64;
+
+template <int NCB, int KC>
+__global__ __launch_bounds__(BX3_THREADS) void k_project_batch_x3(const msm::ProjInst* __restrict__ inst,
+                                                                  const msm::ProjEntry* __restrict__ entries,
+                                                                  int nentries, int ell, int W,
+                                                                  unsigned int* __restrict__ work)
+{
+    extern __shared__ __attribute__((aligned(16))) char bx3_lds[];
+    __shared__ int s_entry;
+    constexpr int PER = KC * NCB * 64;
+    bf16x8* Bh = reinterpret_cast<bf16x8*>(bx3_lds);
+    bf16x8* Bm = Bh + PER;
+    bf16x8* Bl = Bm + PER;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int g = lane >> 4;
+    const int r16 = lane & 15;
+    constexpr int ROWS_PER_TILE = BX3_WAVES * 16;
+    for (;;) {
+        __syncthreads();  // the previous entry is done with the parts and s_entry
+        if (threadIdx.x == 0) s_entry = (int)atomicAdd(work, 1u);
+        __syncthreads();
+        const int e = s_entry;
+        if (e >= nentries) break;
+        const msm::ProjEntry en = entries[e];
+        const msm::ProjInst& in = inst[en.inst];
+        const int d = in.d;
+        const int nkc = (d + 31) / 32;
+        // the instance's R in the B-operand layout of k_project_x3
+        for (int q = threadIdx.x; q < nkc * NCB * 64; q += BX3_THREADS) {
+            const int l = q & 63;
+            const int cb = (q >> 6) % NCB;
+            const int kc = (q >> 6) / NCB;
+            const int c = cb * 16 + (l & 15);
+            const int kb = kc * 32 + 8 * (l >> 4);
+            float v[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) v[i] = (kb + i < d && c < ell) ? in.R[(int64_t)(kb + i) * ell + c] : 0.0f;
+            bf16x8 h, m, lo;
+            split3(v, h, m, lo);
+            Bh[q] = h;
+            Bm[q] = m;
+            Bl[q] = lo;
+        }
+        __syncthreads();
+        const int64_t end = en.row0 + en.rows;
+        // the lane's slice of its row of the tile at r0 (zero past the
+        // entry's rows and past d)
+        auto load_rows = [&](int64_t r0, float (&xv)[KC][8]) {
+            const int64_t row = r0 + (int64_t)wave * 16 + r16;
+            const bool rv = row < end;
+            const float* xr = in.X + (rv ? row : 0) * in.ldx;
+#pragma unroll
+            for (int kc = 0; kc < KC; ++kc) {
+                const int kb = kc * 32 + 8 * g;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) xv[kc][i] = 0.f;
+                if (kc < nkc && rv) {
+                    if (in.vec4 && kb + 7 < d) {
+                        const floatx4 u0 = *reinterpret_cast<const floatx4*>(xr + kb);
+                        const floatx4 u1 = *reinterpret_cast<const floatx4*>(xr + kb + 4);
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            xv[kc][i] = u0[i];
+                            xv[kc][4 + i] = u1[i];
+                        }
+                    } else {
+#pragma unroll
+                        for (int i = 0; i < 8; ++i)
+                            if (kb + i < d) xv[kc][i] = xr[kb + i];
+                    }
+                }
+            }
+        };
+        float xn[KC][8];
+        load_rows(en.row0, xn);
+        for (int64_t r0 = en.row0; r0 < end; r0 += ROWS_PER_TILE) {
+            float xv[KC][8];
+#pragma unroll
+            for (int kc = 0; kc < KC; ++kc)
+#pragma unroll
+                for (int i = 0; i < 8; ++i) xv[kc][i] = xn[kc][i];
+            // the next tile's rows are requested before this tile's products
+            if (r0 + ROWS_PER_TILE < end) load_rows(r0 + ROWS_PER_TILE, xn);
+            floatx4 acc[NCB];
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) acc[cb] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int kc = 0; kc < KC; ++kc) {
+                if (kc < nkc) {
+                    bf16x8 ah, am, al;
+                    split3(xv[kc], ah, am, al);
+#pragma unroll
+                    for (int cb = 0; cb < NCB; ++cb) {
+                        const int q = (kc * NCB + cb) * 64 + lane;
+                        const bf16x8 bh = Bh[q], bm = Bm[q], bl = Bl[q];
+                        // the small terms first, as k_project_x3
+                        floatx4 a = acc[cb];
+                        a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, a, 0, 0, 0);
+                        a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, a, 0, 0, 0);
+                        a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bm, a, 0, 0, 0);
+                        a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bh, a, 0, 0, 0);
+                        a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bm, a, 0, 0, 0);
+                        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, a, 0, 0, 0);
+                    }
+                }
+            }
+            const int orow = lane & 15;
+            const int oword = lane >> 4;
+            uint64_t word = 0;
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) {
+                const uint64_t m0 = __ballot(acc[cb][0] > 0.0f);
+                const uint64_t m1 = __ballot(acc[cb][1] > 0.0f);
+                const uint64_t m2 = __ballot(acc[cb][2] > 0.0f);
+                const uint64_t m3 = __ballot(acc[cb][3] > 0.0f);
+                const int i = orow & 3;
+                const uint64_t mi = i == 0 ? m0 : (i == 1 ? m1 : (i == 2 ? m2 : m3));
+                const uint64_t bits = (mi >> (16 * (orow >> 2))) & 0xFFFFull;
+                if ((cb >> 2) == oword) word |= bits << (16 * (cb & 3));
+            }
+            const int64_t grow = r0 + (int64_t)wave * 16 + orow;
+            if (grow < end && oword < W) {
+                in.S[grow * W + oword] = word;
+                if (in.S2) in.S2[grow * W + oword] = word;
+            }
+        }
+    }
+}
+
 template <int NCB>
 msm_status launch_project(msm_ctx* ctx, const float* X, int64_t n, int d, int64_t ldx,
                           const float* R, int ell, uint64_t* S, hipStream_t stream)
@@ -470,6 +607,28 @@ template <int NCB>
 hipError_t launch_batch(const msm::ProjInst* inst, const msm::ProjEntry* entries, int nentries, int ell,
                         int max_d, int grid, unsigned int* work, hipStream_t stream)
 {
+    // the split form when the parts of R fit in LDS for the deepest instance
+    if constexpr (NCB <= X3_MAX_NCB) {
+        const int kc = max_d <= 128 ? 4 : (max_d <= 256 ? 8 : 0);
+        const size_t lds3 = (size_t)3 * kc * NCB * 64 * sizeof(bf16x8);
+        if (kc && lds3 <= (size_t)X3_LDS_BYTES) {
+            const int W = (ell + 63) / 64;
+            if (kc == 4) {
+                if (lds3 > 65536)
+                    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_project_batch_x3<NCB, 4>),
+                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds3);
+                hipLaunchKernelGGL((k_project_batch_x3<NCB, 4>), dim3((unsigned)grid), dim3(BX3_THREADS), lds3,
+                                   stream, inst, entries, nentries, ell, W, work);
+            } else {
+                if (lds3 > 65536)
+                    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_project_batch_x3<NCB, 8>),
+                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds3);
+                hipLaunchKernelGGL((k_project_batch_x3<NCB, 8>), dim3((unsigned)grid), dim3(BX3_THREADS), lds3,
+                                   stream, inst, entries, nentries, ell, W, work);
+            }
+            return hipGetLastError();
+        }
+    }
     constexpr int RB = batch_rb(NCB);
     const int W = (ell + 63) / 64;
     const int dpad = (max_d + 15) / 16 * 16;
