@@ -209,8 +209,8 @@ def _screen_chosen(X, pairs, eps):
     return m >= X.shape[0] and m0 < m and kept0 * 8 >= m0
 
 
-@pytest.mark.parametrize("d,eps,sigma", [(128, 0.5, (0.05, 0.3)), (100, 0.35, 0.25), (7, 0.12, 0.1),
-                                         (256, 0.6, (0.3, 0.5))])
+@pytest.mark.parametrize("d,eps,sigma", [(128, 0.5, (0.05, 0.3)), (64, 0.4, 0.25), (100, 0.35, 0.25),
+                                         (7, 0.12, 0.1), (256, 0.6, (0.3, 0.5))])
 def test_verify_fp16_screen_matches_fp32_path(msm, ctx, d, eps, sigma):
     """Euclidean lists of at least n pairs, mostly near ones, are screened
     on FP16 rows with a proven bound and only the pairs inside it are
