@@ -63,6 +63,7 @@ struct EnumMem {
     unsigned long long* counter;
     uint32_t* ovfc;
     uint64_t* part;
+    uint32_t* keys;
     uint32_t* counts;
     uint32_t* probe;
     unsigned long long* work;
@@ -74,7 +75,7 @@ struct EnumMem {
 
 // Lays EnumMem out from c.base (NULL: only sizes, in c.off).
 inline EnumMem carve_enum(msm::Carver& c, int Cstd, int Ch, size_t nfam, size_t ndtab, int k, bool probe,
-                          int Cg, int64_t n, int nt, int nb)
+                          int Cg, int64_t n, int nt, int nb, bool keys)
 {
     EnumMem m{};
     m.combos_std = c.take<Combo>((size_t)Cstd);
@@ -87,6 +88,7 @@ inline EnumMem carve_enum(msm::Carver& c, int Cstd, int Ch, size_t nfam, size_t 
     m.counter = c.take<unsigned long long>(4);
     m.ovfc = c.take<uint32_t>(4);
     m.part = c.take<uint64_t>((size_t)Cg * n);
+    m.keys = c.take<uint32_t>(keys ? (size_t)Cg * n : 1);
     m.counts = c.take<uint32_t>((size_t)Cg * nt * nb);
     m.probe = c.take<uint32_t>(probe ? (size_t)(PROBE_HIER + PROBE_STD + 1) * PROBE_BINS : 1);
     m.work = c.take<unsigned long long>(1);
@@ -137,12 +139,17 @@ msm_status run_enumerate(msm_ctx* ctx, const uint64_t* S, int64_t n, int ell, in
     while (sch > SCAT_THREADS && (size_t)sch * 8 + (size_t)nb * 8 > (size_t)150 * 1024) sch /= 2;
     const size_t scat_lds = (size_t)sch * 8 + (size_t)nb * 8;
 
-    // Combinations per launch group, bounded by the memory for them.
-    const size_t per_combo = msm::align_up((size_t)n * 8, 256) + msm::align_up((size_t)nt * nb * 4, 256) +
+    // Combinations per launch group, bounded by the memory for them. The
+    // count pass keeps the masked mixes for the scatter (4 bytes per point
+    // and combination instead of its string), except in the no-allocation
+    // call, whose buffer then holds more points.
+    const bool keys = ext == nullptr;
+    const size_t per_combo = msm::align_up((size_t)n * 8, 256) + (keys ? msm::align_up((size_t)n * 4, 256) : 0) +
+                             msm::align_up((size_t)nt * nb * 4, 256) +
                              msm::align_up((size_t)(nb + 1) * 4, 256) + 3 * msm::align_up((size_t)nb * sizeof(Ovf), 256);
     auto bytes_for = [&](int cg) {
         msm::Carver c;
-        carve_enum(c, Cstd, Ch, fam.size(), dtab.size(), k, hier_cand, cg, n, nt, nb);
+        carve_enum(c, Cstd, Ch, fam.size(), dtab.size(), k, hier_cand, cg, n, nt, nb, keys);
         return c.off;
     };
     const size_t budget = (size_t)3 << 30;
@@ -167,7 +174,7 @@ msm_status run_enumerate(msm_ctx* ctx, const uint64_t* S, int64_t n, int ell, in
     }
     msm::Carver c2;
     c2.base = static_cast<char*>(scr);
-    const EnumMem mem = carve_enum(c2, Cstd, Ch, fam.size(), dtab.size(), k, hier_cand, Cg, n, nt, nb);
+    const EnumMem mem = carve_enum(c2, Cstd, Ch, fam.size(), dtab.size(), k, hier_cand, Cg, n, nt, nb, keys);
     const size_t table_bytes = mem.table_bytes;
     if (ext && table_bytes > msm::NOALLOC_STAGE_BYTES)
         return msm::fail(ctx, MSM_E_UNSUPPORTED,
@@ -232,6 +239,7 @@ msm_status run_enumerate(msm_ctx* ctx, const uint64_t* S, int64_t n, int ell, in
     p.counts = d_counts;
     p.base = d_base;
     p.part = d_part;
+    p.keys = keys ? mem.keys : nullptr;
     p.pairs = pairs;
     p.cap = (unsigned long long)cap;
     p.counter = d_counter;

@@ -144,6 +144,7 @@ struct Params {
     uint32_t* counts;        // [c][t][b] tile counts, then tile offsets
     uint32_t* base;          // [c][nb + 1] bucket starts
     uint64_t* part;          // [c][n] (mix << 32 | index) in bucket order
+    uint32_t* keys;          // [c][n] masked mixes from the count pass, or NULL (the scatter recomputes them)
     uint32_t* pairs;
     unsigned long long cap;
     unsigned long long* counter;
@@ -264,6 +265,7 @@ __global__ __launch_bounds__(PART_THREADS) void k_part_count(Params p)
         const uint32_t mx = masked_mix<W>(s, keep);
         const uint32_t b = p.r1 ? (mx >> (32 - p.r1)) : 0u;
         atomicAdd(&hist[b], 1u);
+        if (p.keys) p.keys[(size_t)cl * (size_t)p.n + (size_t)i] = mx;
     }
     __syncthreads();
     uint32_t* out = p.counts + ((size_t)cl * p.nt + t) * p.nb;
@@ -366,9 +368,14 @@ __global__ __launch_bounds__(SCAT_THREADS) void k_part_scatter(Params p)
             mx[k] = 0u;
             rk[k] = 0u;
             if (e < cnt) {
-                uint64_t s[W];
-                load_string<W>(p.S, (uint64_t)(beg + e), s);
-                mx[k] = masked_mix<W>(s, keep);
+                if (p.keys) {
+                    // the count pass wrote the mix: 4 bytes instead of the string
+                    mx[k] = p.keys[(size_t)cl * (size_t)p.n + (size_t)(beg + e)];
+                } else {
+                    uint64_t s[W];
+                    load_string<W>(p.S, (uint64_t)(beg + e), s);
+                    mx[k] = masked_mix<W>(s, keep);
+                }
                 rk[k] = atomicAdd(&lcnt[p.r1 ? (mx[k] >> shift) : 0u], 1u);
             }
         }
