@@ -123,9 +123,11 @@ def algorithmic(kernel, w, n, C, mH, mE, W, launches=1, hid=None):
     if kernel == "k_mlp_fused" and hid:
         return 2.0 * n * (w.d * hid + hid * w.ell) / 1e12, "TFLOP/s", "mfma_bf16"
     if kernel == "k_part_count":
-        return n * C * sb / 1e9, "GB/s", "hbm"
+        # the string read and its 4-byte mix written for the scatter
+        return n * C * (sb + 4) / 1e9, "GB/s", "hbm"
     if kernel == "k_part_scatter":
-        return n * C * (sb + 8) / 1e9, "GB/s", "hbm"
+        # the mix read and the 8-byte entry written
+        return n * C * (4 + 8) / 1e9, "GB/s", "hbm"
     if kernel == "k_bucket":
         # per point and combination: its 8-byte partition entry and its string
         return (n * C * (8 + sb) + mH * 8 / max(launches, 1)) / 1e9, "GB/s", "hbm"
